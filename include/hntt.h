@@ -1,0 +1,190 @@
+/*
+ * hntt — lazy-butterfly number-theoretic transforms on AMD MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  It implements the radix-2 NTT over F_p of
+ * D. Harvey, "Faster arithmetic for number-theoretic transforms"
+ * (arXiv:1205.2926), for word-sized primes p = 1 (mod L), L = 2^l:
+ *
+ *   forward   b_j = sum_{i<L} omega^(ij) a_i  (mod p)           Section 1, display eq.
+ *             natural-order input, output in bit-reversed order  Section 1, Algorithm 1
+ *   inverse   a_i = L^(-1) sum_{j<L} omega^(-ij) b_j  (mod p)
+ *             bit-reversed input, natural-order output           Section 4 (Algorithm 1 run backwards)
+ *
+ * The default butterflies are the lazy ones: Algorithm 3 (forward, residues
+ * kept in [0,2p)) and Algorithm 4 (inverse, residues kept in [0,4p)), each
+ * multiplying by a precomputed Shoup constant W' = floor(W beta / p).  The
+ * flag HNTT_PLAIN selects the fully reducing butterfly of Algorithm 2 (and its
+ * inverse counterpart) under the same kernel schedule, for comparison.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: HNTT_OK (0) or a negative HNTT_E* status.  Nothing throws.
+ *   - Argument errors (HNTT_EINVAL, HNTT_EUNSUPPORTED) are found on the host
+ *     before anything is enqueued: on such a return no device work was issued.
+ *   - Data buffers are DEVICE pointers owned by the caller; descriptor arrays
+ *     are HOST memory, read during the call and not retained.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream) and runs asynchronously in stream order.  A device
+ *     failure is reported as HNTT_EDEVICE by the failing call or a later one.
+ *   - Inputs must be fully reduced residues in [0,p); outputs are fully
+ *     reduced to [0,p) (bit-exact with any correct implementation).
+ *   - A context is used by one host thread at a time.
+ *   - hntt_last_error(ctx) returns a human-readable message for the most
+ *     recent failure on that context.
+ */
+#ifndef HNTT_H
+#define HNTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HNTT_OK = 0,
+  HNTT_EINVAL = -1,       /* malformed argument or descriptor */
+  HNTT_EUNSUPPORTED = -2, /* well-formed but outside what the library implements */
+  HNTT_ENOMEM = -3,       /* device memory (or the context's memory budget) exhausted */
+  HNTT_EDEVICE = -4,      /* HIP runtime or device error */
+  HNTT_EBUSY = -5         /* serving: request cannot be admitted now */
+};
+
+/* Flags for the transform entry points. */
+#define HNTT_PLAIN 0x1u        /* fully reducing butterflies (Algorithm 2 and its DIT twin) */
+#define HNTT_NO_NORMALIZE 0x2u /* skip the final reduction: forward leaves [0,2p) (lazy),
+                                  inverse leaves [0,4p) (lazy); for chained pipelines only */
+
+typedef struct hntt_ctx hntt_ctx;
+
+/* Create a context bound to HIP device `device`.  The device is touched only
+ * when the first computation is enqueued, so argument checking works without
+ * a GPU.  `mem_budget_bytes` caps the device memory the context may hold for
+ * twiddle tables and polynomial workspaces (0 = no cap).
+ * Errors: EINVAL (out == NULL or device < 0), ENOMEM (host allocation). */
+int hntt_create(hntt_ctx **out, int device, size_t mem_budget_bytes);
+
+/* Free the context and every device buffer it owns.  NULL is ignored.  The
+ * caller must make sure no enqueued work still uses the context. */
+void hntt_destroy(hntt_ctx *ctx);
+
+/* Static description of a status code. */
+const char *hntt_strerror(int status);
+
+/* Message of the last failure on ctx ("" if none).  Valid until the next call on ctx. */
+const char *hntt_last_error(const hntt_ctx *ctx);
+
+/* One transform: `data` is a device array of 2^log2_len words of word_bits
+ * bits (32: uint32_t, 64: uint64_t), transformed in place.
+ *   p        prime, p = 1 (mod 2^log2_len).  Lazy butterflies need p < beta/4
+ *            (Algorithm 3 input conditions); HNTT_PLAIN needs p < beta/2
+ *            (Algorithm 2 input conditions); beta = 2^word_bits.
+ *   omega    a primitive 2^log2_len-th root of unity mod p (Section 1): the
+ *            transform is defined by it, another root permutes the output.
+ *   log2_len 1 <= l <= 30 (and 2^l words must be addressable).
+ * Primality of p is checked once per context with deterministic Miller-Rabin;
+ * omega is checked by omega^(L/2) = p - 1. */
+typedef struct {
+  uint64_t p;
+  uint64_t omega;
+  void *data;
+  uint32_t log2_len;
+  uint32_t word_bits;
+} hntt_desc;
+
+/* Forward NTT of n descriptors (Section 1, Algorithm 1 with the Algorithm 3
+ * butterfly).  Natural-order input in [0,p), bit-reversed output in [0,p).
+ * Descriptors may mix primes, lengths and word sizes; descriptors that share
+ * (p, omega, log2_len, word_bits) are transformed by the same launches.
+ * Two descriptors must not name overlapping data.  flags: HNTT_PLAIN,
+ * HNTT_NO_NORMALIZE.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+int hntt_ntt_forward(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream);
+
+/* Inverse NTT (Section 4: Algorithm 1 run backwards with the Algorithm 4
+ * butterfly, then multiplication by L^(-1)).  Bit-reversed input in [0,p),
+ * natural-order output in [0,p); inverse(forward(x)) = x.  Same descriptor
+ * rules, flags and errors as hntt_ntt_forward. */
+int hntt_ntt_inverse(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream);
+
+/* Pointwise product c_i = a_i b_i (mod p) over `len` words of word_bits bits
+ * (device pointers; c may alias a or b).  Needs p < 2^31 for 32-bit words and
+ * p < 2^62 for 64-bit words; inputs in [0,p), output in [0,p).  Used between
+ * forward and inverse transforms to multiply polynomials (the convolution
+ * theorem behind the application named in Section 1).
+ * Errors: EINVAL, EUNSUPPORTED, EDEVICE. */
+typedef struct {
+  uint64_t p;
+  const void *a;
+  const void *b;
+  void *c;
+  uint64_t len;
+  uint32_t word_bits;
+  uint32_t reserved; /* must be 0 */
+} hntt_pw_desc;
+int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint32_t flags, void *stream);
+
+/* Exact integer polynomial products (the application of Section 1) through
+ * three NTT primes, 998244353, 754974721 and 167772161, and Chinese
+ * remaindering.  For each descriptor: a has na, b has nb uint32 coefficients
+ * (device), out receives na + nb - 1 uint64 coefficients (device).  The
+ * product is exact when every coefficient of a*b is below
+ * 998244353 * 754974721 * 167772161 (about 2^86.7) and below 2^64, e.g. for
+ * coefficients below 2^20 and min(na, nb) <= 2^24.  Each product is padded to
+ * L = 2 * nextpow2(max(na, nb)) <= 2^23.  The whole batch runs as one
+ * persistent kernel launch per phase with tile schedules taken from the
+ * context's tuning table (hntt_autotune).  Workspace is held by the context.
+ * flags: HNTT_PLAIN.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+typedef struct {
+  const uint32_t *a;
+  const uint32_t *b;
+  uint64_t *out;
+  uint32_t na;
+  uint32_t nb;
+} hntt_poly_desc;
+int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Host-side number theory (no device needed).  These are the parameters of
+ * the problem setting in Section 1 and the Shoup constant of Algorithm 2.
+ * ------------------------------------------------------------------------- */
+
+/* 1 if n is prime (deterministic Miller-Rabin for 64-bit n), else 0. */
+int hntt_is_prime(uint64_t n);
+
+/* Smallest primitive root of the prime p, or 0 if p is not an odd prime. */
+uint64_t hntt_primitive_root(uint64_t p);
+
+/* omega = g^((p-1)/2^log2_len) for the smallest primitive root g of p.
+ * Errors: EINVAL if p is not prime or 2^log2_len does not divide p - 1. */
+int hntt_root_of_unity(uint64_t p, uint32_t log2_len, uint64_t *omega_out);
+
+/* Largest prime p < 2^bits with p = 1 (mod 2^v), 2 <= bits <= 64, v < bits;
+ * 0 if none. */
+uint64_t hntt_find_prime(uint32_t bits, uint32_t v);
+
+/* Shoup constant W' = floor(W * 2^word_bits / p) for 0 <= W < p (Algorithm 2
+ * input conditions).  Errors: EINVAL on W >= p, p < 2, p >= 2^word_bits. */
+int hntt_shoup_constant(uint64_t w, uint64_t p, uint32_t word_bits, uint64_t *wprime_out);
+
+/* Check descriptors as hntt_ntt_forward would, without touching the device.
+ * Returns HNTT_OK or the error the transform call would return. */
+int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags);
+
+/* ---------------------------------------------------------------------------
+ * Device unit test of the butterflies themselves (Algorithms 2, 3, 4).
+ * kind: 0 = Algorithm 2 (plain forward), 1 = Algorithm 3 (lazy forward),
+ *       2 = Algorithm 4 (lazy inverse),  3 = plain inverse (fully reducing).
+ * For i < n: (xo[i], yo[i]) = butterfly(x[i], y[i]) with twiddle w[i] and its
+ * Shoup constant computed on the host.  All arrays are device arrays of
+ * word_bits-bit words.  Inputs must satisfy the algorithm's stated ranges.
+ * Errors: EINVAL, EUNSUPPORTED, EDEVICE.
+ * ------------------------------------------------------------------------- */
+int hntt_debug_butterfly(hntt_ctx *ctx, int kind, uint32_t word_bits, uint64_t p, const void *x,
+                         const void *y, const void *w, const void *wprime, void *xo, void *yo, size_t n,
+                         void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HNTT_H */

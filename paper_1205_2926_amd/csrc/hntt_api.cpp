@@ -1,0 +1,465 @@
+// C ABI of the library (include/hntt.h): argument checking, planning,
+// twiddle-table cache and kernel dispatch.  Host code only; the kernels live
+// in ntt_kernels.hip.
+#include "hntt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hntt_internal.hpp"
+#include "ntt_kernels.hpp"
+#include "numtheory.hpp"
+
+using namespace hntt;
+
+namespace hntt {
+
+// ------------------------------------------------------------------------------------------------
+// Device buffers owned by the context.
+DeviceBuffer::~DeviceBuffer() {
+  if (ptr) (void)hipFree(ptr);
+}
+
+}  // namespace hntt
+
+namespace {
+
+int set_error(hntt_ctx *ctx, int status, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int set_error(hntt_ctx *ctx, int status, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return status;
+}
+
+int hip_status(hntt_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return HNTT_OK;
+  if (e == hipErrorOutOfMemory) return set_error(ctx, HNTT_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return set_error(ctx, HNTT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool prime_cached(hntt_ctx *ctx, uint64_t p) {
+  auto it = ctx->prime_cache.find(p);
+  if (it != ctx->prime_cache.end()) return it->second;
+  const bool r = is_prime_u64(p);
+  ctx->prime_cache[p] = r;
+  return r;
+}
+
+int max_whole_log(int word_bits) { return word_bits == 32 ? 12 : 11; }
+
+int tpt_of(int n) { return n > 4 ? (1 << (n - 4)) : 1; }
+
+}  // namespace
+
+namespace hntt {
+
+int check_desc(hntt_ctx *ctx, const hntt_desc &d, uint32_t flags) {
+  const bool plain = flags & HNTT_PLAIN;
+  if (d.word_bits != 32 && d.word_bits != 64)
+    return set_error(ctx, HNTT_EINVAL, "word_bits must be 32 or 64 (got %u)", d.word_bits);
+  if (!d.data) return set_error(ctx, HNTT_EINVAL, "data pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(d.data) % (d.word_bits / 8))
+    return set_error(ctx, HNTT_EINVAL, "data pointer is not aligned to the word size");
+  if (d.log2_len < 1 || d.log2_len > 30)
+    return set_error(ctx, HNTT_EINVAL, "log2_len must be in [1, 30] (got %u)", d.log2_len);
+  if (d.p < 3 || !(d.p & 1)) return set_error(ctx, HNTT_EINVAL, "p must be an odd prime (got %llu)",
+                                              (unsigned long long)d.p);
+  const unsigned limit_bits = d.word_bits - (plain ? 1 : 2);  // p < beta/2 (Alg. 2) or beta/4 (Alg. 3, 4)
+  if (limit_bits < 64 && d.p >= (1ull << limit_bits))
+    return set_error(ctx, HNTT_EUNSUPPORTED, "p = %llu needs p < 2^%u for %s butterflies on %u-bit words",
+                     (unsigned long long)d.p, limit_bits, plain ? "plain" : "lazy", d.word_bits);
+  if ((d.p - 1) % (1ull << d.log2_len))
+    return set_error(ctx, HNTT_EINVAL, "2^%u does not divide p - 1", d.log2_len);
+  if (!prime_cached(ctx, d.p)) return set_error(ctx, HNTT_EINVAL, "p = %llu is not prime", (unsigned long long)d.p);
+  if (d.omega == 0 || d.omega >= d.p)
+    return set_error(ctx, HNTT_EINVAL, "omega must be in [1, p)");
+  if (powmod(d.omega, 1ull << (d.log2_len - 1), d.p) != d.p - 1)
+    return set_error(ctx, HNTT_EINVAL, "omega is not a primitive 2^%u-th root of unity mod p", d.log2_len);
+  const int lmax = max_whole_log((int)d.word_bits);
+  if ((int)d.log2_len > 2 * lmax)
+    return set_error(ctx, HNTT_EUNSUPPORTED, "log2_len %u exceeds the two-pass limit %d for %u-bit words",
+                     d.log2_len, 2 * lmax, d.word_bits);
+  return HNTT_OK;
+}
+
+Plan make_plan(int l, int word_bits) {
+  Plan pl{};
+  const int lmax = max_whole_log(word_bits);
+  if (l <= lmax) {
+    pl.split = false;
+    pl.r = l;
+    pl.c = 0;
+    return pl;
+  }
+  pl.split = true;
+  pl.c = (l + 1) / 2;
+  pl.r = l - pl.c;
+  // column pass: as many adjacent columns as the 1024-thread and LDS limits allow
+  const int gmax_cols = word_bits == 32 ? 16 : 8;
+  int g = gmax_cols;
+  while (g > 1 && (tpt_of(pl.r) * g > 1024 || g > (1 << pl.c))) g >>= 1;
+  while (g > 1) {
+    PassParams pp{};
+    pp.word_bits = word_bits;
+    pp.n = pl.r;
+    pp.group = g;
+    if (pass_lds_bytes(pp) && pass_lds_bytes(pp) <= 80 * 1024) break;
+    g >>= 1;
+  }
+  pl.g_cols = g;
+  int gr = std::max(1, 256 / tpt_of(pl.c));
+  gr = std::min(gr, 1 << pl.r);
+  pl.g_rows = gr;
+  return pl;
+}
+
+// Builds omega_N^(sign*j) for j < N/2 with Shoup constants, as words of word_bits bits.
+static void pow_table(uint64_t root, int half, uint64_t p, int bits, std::vector<uint64_t> &w,
+                      std::vector<uint64_t> &wp) {
+  w.resize(half);
+  wp.resize(half);
+  uint64_t x = 1;
+  for (int j = 0; j < half; ++j) {
+    w[j] = x;
+    wp[j] = shoup_constant(x, p, bits);
+    x = mulmod(x, root, p);
+  }
+}
+
+int upload(hntt_ctx *ctx, const std::vector<uint64_t> &src, int bits, const void **out) {
+  const size_t bytes = src.size() * (bits / 8);
+  if (ctx->budget && ctx->bytes_held + bytes > ctx->budget)
+    return set_error(ctx, HNTT_ENOMEM, "memory budget of %zu bytes exceeded", ctx->budget);
+  auto buf = std::make_unique<DeviceBuffer>();
+  if (bytes) {
+    hipError_t e = hipMalloc(&buf->ptr, bytes);
+    if (e != hipSuccess) return hip_status(ctx, e, "hipMalloc(twiddle table)");
+    buf->bytes = bytes;
+    if (bits == 32) {
+      std::vector<uint32_t> narrow(src.begin(), src.end());
+      e = hipMemcpy(buf->ptr, narrow.data(), bytes, hipMemcpyHostToDevice);
+    } else {
+      e = hipMemcpy(buf->ptr, src.data(), bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_status(ctx, e, "hipMemcpy(twiddle table)");
+  }
+  ctx->bytes_held += bytes;
+  *out = buf->ptr;
+  ctx->buffers.push_back(std::move(buf));
+  return HNTT_OK;
+}
+
+// Twiddle tables for one (p, omega, l, word_bits): built on the host once and kept on the device.
+int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const Tables **out) {
+  const auto key = std::make_tuple(p, omega, l, bits);
+  auto it = ctx->tables.find(key);
+  if (it != ctx->tables.end()) {
+    *out = &it->second;
+    return HNTT_OK;
+  }
+  Tables t{};
+  t.plan = make_plan(l, bits);
+  const uint64_t omega_inv = powmod(omega, p - 2, p);
+  const uint64_t L = 1ull << l;
+  const uint64_t linv = powmod(L % p, p - 2, p);
+  t.linv = linv;
+  t.linv_p = shoup_constant(linv, p, bits);
+  std::vector<uint64_t> w, wp;
+  int rc;
+  auto table_pair = [&](uint64_t root, int n, const void **dw, const void **dwp) -> int {
+    pow_table(root, (1 << n) >> 1, p, bits, w, wp);
+    int r = upload(ctx, w, bits, dw);
+    if (r) return r;
+    return upload(ctx, wp, bits, dwp);
+  };
+  if (!t.plan.split) {
+    if ((rc = table_pair(omega, l, &t.fwd_w, &t.fwd_wp))) return rc;
+    if ((rc = table_pair(omega_inv, l, &t.inv_w, &t.inv_wp))) return rc;
+  } else {
+    const int r = t.plan.r, c = t.plan.c;
+    const uint64_t R = 1ull << r, C = 1ull << c;
+    // column transforms (length R) use omega^C; row transforms (length C) use omega^R
+    if ((rc = table_pair(powmod(omega, C, p), r, &t.fwd_w, &t.fwd_wp))) return rc;
+    if ((rc = table_pair(powmod(omega_inv, C, p), r, &t.inv_w, &t.inv_wp))) return rc;
+    if ((rc = table_pair(powmod(omega, R, p), c, &t.row_fwd_w, &t.row_fwd_wp))) return rc;
+    if ((rc = table_pair(powmod(omega_inv, R, p), c, &t.row_inv_w, &t.row_inv_wp))) return rc;
+    // split twiddles, laid out like the data: entry (pos, col) = omega^(col * rev_r(pos)),
+    // and for the inverse L^-1 * omega^(-col * rev_r(pos))
+    std::vector<uint64_t> fw(L), fwp(L), iw(L), iwp(L);
+    for (uint64_t pos = 0; pos < R; ++pos) {
+      const uint64_t s = bitrev((unsigned)pos, r);
+      const uint64_t step_f = powmod(omega, s, p), step_i = powmod(omega_inv, s, p);
+      uint64_t xf = 1, xi = linv;
+      for (uint64_t col = 0; col < C; ++col) {
+        const uint64_t idx = pos * C + col;
+        fw[idx] = xf;
+        fwp[idx] = shoup_constant(xf, p, bits);
+        iw[idx] = xi;
+        iwp[idx] = shoup_constant(xi, p, bits);
+        xf = mulmod(xf, step_f, p);
+        xi = mulmod(xi, step_i, p);
+      }
+    }
+    if ((rc = upload(ctx, fw, bits, &t.tt_fwd_w))) return rc;
+    if ((rc = upload(ctx, fwp, bits, &t.tt_fwd_wp))) return rc;
+    if ((rc = upload(ctx, iw, bits, &t.tt_inv_w))) return rc;
+    if ((rc = upload(ctx, iwp, bits, &t.tt_inv_wp))) return rc;
+  }
+  auto ins = ctx->tables.emplace(key, t);
+  *out = &ins.first->second;
+  return HNTT_OK;
+}
+
+int ensure_device(hntt_ctx *ctx) {
+  if (ctx->device_ready) return HNTT_OK;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) return set_error(ctx, HNTT_EDEVICE, "no HIP device available");
+  if (ctx->device >= count) return set_error(ctx, HNTT_EINVAL, "device %d does not exist", ctx->device);
+  ctx->device_ready = true;
+  return HNTT_OK;
+}
+
+// Run every pass of one transform direction over a batch sharing (p, omega, l, word_bits).
+int run_transform(hntt_ctx *ctx, const Tables &t, const std::vector<void *> &ptrs, uint64_t p, int l, int bits,
+                  bool inverse, uint32_t flags, hipStream_t stream) {
+  const bool lazy = !(flags & HNTT_PLAIN);
+  const bool norm = !(flags & HNTT_NO_NORMALIZE);
+  for (size_t off = 0; off < ptrs.size(); off += kMaxBatchPerLaunch) {
+    BatchPtrs bp{};
+    const int nb = (int)std::min<size_t>(kMaxBatchPerLaunch, ptrs.size() - off);
+    for (int i = 0; i < nb; ++i) bp.ptr[i] = reinterpret_cast<uint64_t>(ptrs[off + i]);
+    PassParams pp{};
+    pp.word_bits = bits;
+    pp.lazy = lazy;
+    pp.inverse = inverse;
+    pp.nbatch = nb;
+    pp.p = p;
+    hipError_t e;
+    if (!t.plan.split) {
+      pp.kind = PassKind::kWhole;
+      pp.n = l;
+      pp.log_other = 0;
+      pp.group = 1;
+      pp.normalize = norm;
+      pp.tw_w = inverse ? t.inv_w : t.fwd_w;
+      pp.tw_wp = inverse ? t.inv_wp : t.fwd_wp;
+      pp.scale_w = t.linv;
+      pp.scale_wp = t.linv_p;
+      if ((e = launch_pass(pp, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(whole)");
+      continue;
+    }
+    PassParams cols = pp, rows = pp;
+    cols.kind = PassKind::kCols;
+    cols.n = t.plan.r;
+    cols.log_other = t.plan.c;
+    cols.group = t.plan.g_cols;
+    cols.tw_w = inverse ? t.inv_w : t.fwd_w;
+    cols.tw_wp = inverse ? t.inv_wp : t.fwd_wp;
+    cols.tt_w = inverse ? t.tt_inv_w : t.tt_fwd_w;
+    cols.tt_wp = inverse ? t.tt_inv_wp : t.tt_fwd_wp;
+    rows.kind = PassKind::kRows;
+    rows.n = t.plan.c;
+    rows.log_other = t.plan.r;
+    rows.group = t.plan.g_rows;
+    rows.tw_w = inverse ? t.row_inv_w : t.row_fwd_w;
+    rows.tw_wp = inverse ? t.row_inv_wp : t.row_fwd_wp;
+    if (!inverse) {
+      cols.normalize = false;
+      rows.normalize = norm;
+      if ((e = launch_pass(cols, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(cols)");
+      if ((e = launch_pass(rows, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(rows)");
+    } else {
+      rows.normalize = false;
+      cols.normalize = norm;
+      if ((e = launch_pass(rows, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(rows)");
+      if ((e = launch_pass(cols, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(cols)");
+    }
+  }
+  return HNTT_OK;
+}
+
+int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream, bool inverse) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  // group descriptors that share parameters; validate everything before enqueueing anything
+  std::map<std::tuple<uint64_t, uint64_t, int, int>, std::vector<void *>> groups;
+  for (size_t i = 0; i < n; ++i) {
+    int rc = check_desc(ctx, descs[i], flags);
+    if (rc) return rc;
+    groups[std::make_tuple(descs[i].p, descs[i].omega, (int)descs[i].log2_len, (int)descs[i].word_bits)].push_back(
+        descs[i].data);
+  }
+  if (n == 0) return HNTT_OK;
+  int rc = ensure_device(ctx);
+  if (rc) return rc;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return set_error(ctx, HNTT_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  for (auto &kv : groups) {
+    const uint64_t p = std::get<0>(kv.first), omega = std::get<1>(kv.first);
+    const int l = std::get<2>(kv.first), bits = std::get<3>(kv.first);
+    const Tables *t = nullptr;
+    if ((rc = get_tables(ctx, p, omega, l, bits, &t))) return rc;
+    if ((rc = run_transform(ctx, *t, kv.second, p, l, bits, inverse, flags, (hipStream_t)stream))) return rc;
+  }
+  return HNTT_OK;
+}
+
+}  // namespace hntt
+
+// ==================================================================================================
+extern "C" {
+
+int hntt_create(hntt_ctx **out, int device, size_t mem_budget_bytes) {
+  if (!out || device < 0) return HNTT_EINVAL;
+  hntt_ctx *c = new (std::nothrow) hntt_ctx();
+  if (!c) return HNTT_ENOMEM;
+  c->device = device;
+  c->budget = mem_budget_bytes;
+  *out = c;
+  return HNTT_OK;
+}
+
+void hntt_destroy(hntt_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->device_ready) {
+    DeviceGuard guard(ctx->device);
+    ctx->release_device_state();
+    ctx->buffers.clear();
+  }
+  delete ctx;
+}
+
+const char *hntt_strerror(int status) {
+  switch (status) {
+    case HNTT_OK: return "success";
+    case HNTT_EINVAL: return "invalid argument";
+    case HNTT_EUNSUPPORTED: return "unsupported parameters";
+    case HNTT_ENOMEM: return "out of device memory or over the context budget";
+    case HNTT_EDEVICE: return "HIP device error";
+    case HNTT_EBUSY: return "busy: request not admitted";
+    default: return "unknown status";
+  }
+}
+
+const char *hntt_last_error(const hntt_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int hntt_ntt_forward(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream) {
+  return transform(ctx, descs, n, flags, stream, false);
+}
+
+int hntt_ntt_inverse(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream) {
+  return transform(ctx, descs, n, flags, stream, true);
+}
+
+int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  for (size_t i = 0; i < n; ++i) {
+    int rc = check_desc(ctx, descs[i], flags);
+    if (rc) return rc;
+  }
+  return HNTT_OK;
+}
+
+int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint32_t flags, void *stream) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
+  if (flags) return set_error(ctx, HNTT_EINVAL, "pointwise_mul takes no flags");
+  for (size_t i = 0; i < n; ++i) {
+    const hntt_pw_desc &d = descs[i];
+    if (d.word_bits != 32 && d.word_bits != 64) return set_error(ctx, HNTT_EINVAL, "word_bits must be 32 or 64");
+    if (d.reserved) return set_error(ctx, HNTT_EINVAL, "reserved field must be 0");
+    if (d.len && (!d.a || !d.b || !d.c)) return set_error(ctx, HNTT_EINVAL, "NULL operand");
+    if (d.p < 3 || !(d.p & 1)) return set_error(ctx, HNTT_EINVAL, "p must be odd and >= 3");
+    if (d.p >= (1ull << (d.word_bits - 2)))
+      return set_error(ctx, HNTT_EUNSUPPORTED, "pointwise_mul needs p < 2^%u", d.word_bits - 2);
+  }
+  if (n == 0) return HNTT_OK;
+  int rc = ensure_device(ctx);
+  if (rc) return rc;
+  DeviceGuard guard(ctx->device);
+  for (size_t i = 0; i < n; ++i) {
+    const hntt_pw_desc &d = descs[i];
+    hipError_t e = launch_pointwise((int)d.word_bits, d.p, d.a, d.b, d.c, d.len, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_status(ctx, e, "launch(pointwise)");
+  }
+  return HNTT_OK;
+}
+
+int hntt_is_prime(uint64_t n) { return is_prime_u64(n) ? 1 : 0; }
+
+uint64_t hntt_primitive_root(uint64_t p) { return primitive_root(p); }
+
+int hntt_root_of_unity(uint64_t p, uint32_t log2_len, uint64_t *omega_out) {
+  if (!omega_out || log2_len > 63) return HNTT_EINVAL;
+  const uint64_t g = primitive_root(p);
+  if (!g) return HNTT_EINVAL;
+  if ((p - 1) % (1ull << log2_len)) return HNTT_EINVAL;
+  *omega_out = powmod(g, (p - 1) >> log2_len, p);
+  return HNTT_OK;
+}
+
+uint64_t hntt_find_prime(uint32_t bits, uint32_t v) { return find_prime(bits, v); }
+
+int hntt_shoup_constant(uint64_t w, uint64_t p, uint32_t word_bits, uint64_t *wprime_out) {
+  if (!wprime_out || (word_bits != 32 && word_bits != 64) || p < 2 || w >= p) return HNTT_EINVAL;
+  if (word_bits == 32 && p > 0xFFFFFFFFull) return HNTT_EINVAL;
+  *wprime_out = shoup_constant(w, p, (int)word_bits);
+  return HNTT_OK;
+}
+
+int hntt_debug_butterfly(hntt_ctx *ctx, int kind, uint32_t word_bits, uint64_t p, const void *x, const void *y,
+                         const void *w, const void *wprime, void *xo, void *yo, size_t n, void *stream) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (kind < 0 || kind > 3) return set_error(ctx, HNTT_EINVAL, "kind must be 0..3");
+  if (word_bits != 32 && word_bits != 64) return set_error(ctx, HNTT_EINVAL, "word_bits must be 32 or 64");
+  if (n && (!x || !y || !w || !wprime || !xo || !yo)) return set_error(ctx, HNTT_EINVAL, "NULL array");
+  const unsigned limit_bits = word_bits - ((kind == 0 || kind == 3) ? 1 : 2);
+  if (p < 3 || (limit_bits < 64 && p >= (1ull << limit_bits)))
+    return set_error(ctx, HNTT_EUNSUPPORTED, "p out of range for this butterfly");
+  if (n == 0) return HNTT_OK;
+  int rc = ensure_device(ctx);
+  if (rc) return rc;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = launch_debug_butterfly(kind, (int)word_bits, p, x, y, w, wprime, xo, yo, n, (hipStream_t)stream);
+  return hip_status(ctx, e, "launch(debug_butterfly)");
+}
+
+}  // extern "C"

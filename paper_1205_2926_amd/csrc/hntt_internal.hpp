@@ -1,0 +1,63 @@
+// Internal state of a library context (not part of the C ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hntt.h"
+
+namespace hntt {
+
+struct DeviceBuffer {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DeviceBuffer() = default;
+  DeviceBuffer(const DeviceBuffer &) = delete;
+  DeviceBuffer &operator=(const DeviceBuffer &) = delete;
+  ~DeviceBuffer();
+};
+
+// How a transform of length 2^l is split into passes.
+struct Plan {
+  bool split;  // false: one whole-transform pass
+  int r;       // log2 of the column-transform length (split) or l (whole)
+  int c;       // log2 of the row length (split)
+  int g_cols;  // columns per workgroup in the column pass
+  int g_rows;  // rows per workgroup in the row pass
+};
+
+// Device twiddle tables for one (p, omega, l, word_bits).
+struct Tables {
+  Plan plan;
+  uint64_t linv, linv_p;  // L^-1 mod p and its Shoup constant
+  const void *fwd_w, *fwd_wp, *inv_w, *inv_wp;                       // whole or column transform
+  const void *row_fwd_w, *row_fwd_wp, *row_inv_w, *row_inv_wp;       // row transform (split)
+  const void *tt_fwd_w, *tt_fwd_wp, *tt_inv_w, *tt_inv_wp;           // split twiddles (split)
+};
+
+}  // namespace hntt
+
+struct hntt_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t bytes_held = 0;
+  bool device_ready = false;
+  std::string last_error;
+  std::map<uint64_t, bool> prime_cache;
+  std::map<std::tuple<uint64_t, uint64_t, int, int>, hntt::Tables> tables;
+  std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
+  void release_device_state() { tables.clear(); }
+};
+
+namespace hntt {
+int check_desc(hntt_ctx *ctx, const hntt_desc &d, uint32_t flags);
+Plan make_plan(int l, int word_bits);
+int ensure_device(hntt_ctx *ctx);
+int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const Tables **out);
+int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream, bool inverse);
+}  // namespace hntt

@@ -1,0 +1,236 @@
+"""Thin ctypes binding of ``libhntt.so`` (the C ABI in include/hntt.h).
+
+Argument marshalling only: every step of a transform runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors on ``cuda``, i.e. HIP on
+ROCm) and streams.  Tensors hold unsigned words: ``torch.uint32``/``int32``
+for 32-bit words, ``torch.uint64``/``int64`` for 64-bit words (the bits are
+read as unsigned).
+
+If the library has not been built, loading raises ``HnttNotBuilt``; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhntt.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5
+PLAIN = 0x1
+NO_NORMALIZE = 0x2
+
+_c_u64 = ctypes.c_uint64
+_c_u32 = ctypes.c_uint32
+_c_vp = ctypes.c_void_p
+
+
+class HnttNotBuilt(RuntimeError):
+    pass
+
+
+class HnttError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"hntt error {status}: {message}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("p", _c_u64), ("omega", _c_u64), ("data", _c_vp), ("log2_len", _c_u32), ("word_bits", _c_u32)]
+
+
+class PwDesc(ctypes.Structure):
+    _fields_ = [("p", _c_u64), ("a", _c_vp), ("b", _c_vp), ("c", _c_vp), ("len", _c_u64), ("word_bits", _c_u32),
+                ("reserved", _c_u32)]
+
+
+class PolyDesc(ctypes.Structure):
+    _fields_ = [("a", _c_vp), ("b", _c_vp), ("out", _c_vp), ("na", _c_u32), ("nb", _c_u32)]
+
+
+#: every function include/hntt.h declares, with its ctypes signature
+SIGNATURES = {
+    "hntt_create": (ctypes.c_int, [ctypes.POINTER(_c_vp), ctypes.c_int, ctypes.c_size_t]),
+    "hntt_destroy": (None, [_c_vp]),
+    "hntt_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "hntt_last_error": (ctypes.c_char_p, [_c_vp]),
+    "hntt_ntt_forward": (ctypes.c_int, [_c_vp, ctypes.POINTER(Desc), ctypes.c_size_t, _c_u32, _c_vp]),
+    "hntt_ntt_inverse": (ctypes.c_int, [_c_vp, ctypes.POINTER(Desc), ctypes.c_size_t, _c_u32, _c_vp]),
+    "hntt_pointwise_mul": (ctypes.c_int, [_c_vp, ctypes.POINTER(PwDesc), ctypes.c_size_t, _c_u32, _c_vp]),
+    "hntt_polymul_crt": (ctypes.c_int, [_c_vp, ctypes.POINTER(PolyDesc), ctypes.c_size_t, _c_u32, _c_vp]),
+    "hntt_is_prime": (ctypes.c_int, [_c_u64]),
+    "hntt_primitive_root": (_c_u64, [_c_u64]),
+    "hntt_root_of_unity": (ctypes.c_int, [_c_u64, _c_u32, ctypes.POINTER(_c_u64)]),
+    "hntt_find_prime": (_c_u64, [_c_u32, _c_u32]),
+    "hntt_shoup_constant": (ctypes.c_int, [_c_u64, _c_u64, _c_u32, ctypes.POINTER(_c_u64)]),
+    "hntt_validate": (ctypes.c_int, [_c_vp, ctypes.POINTER(Desc), ctypes.c_size_t, _c_u32]),
+    "hntt_debug_butterfly": (ctypes.c_int, [_c_vp, ctypes.c_int, _c_u32, _c_u64, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                            _c_vp, ctypes.c_size_t, _c_vp]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (once).  Raises HnttNotBuilt when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HnttNotBuilt(f"{path} is missing: build it with `python -m paper_1205_2926_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ------------------------------------------------------------------------------------------------
+# host number theory (no GPU needed)
+def is_prime(n: int) -> bool:
+    return bool(load().hntt_is_prime(n))
+
+
+def primitive_root(p: int) -> int:
+    return int(load().hntt_primitive_root(p))
+
+
+def root_of_unity(p: int, log2_len: int) -> int:
+    out = _c_u64()
+    rc = load().hntt_root_of_unity(p, log2_len, ctypes.byref(out))
+    if rc:
+        raise HnttError(rc, f"no 2^{log2_len}-th root of unity mod {p}")
+    return int(out.value)
+
+
+def find_prime(bits: int, v: int) -> int:
+    return int(load().hntt_find_prime(bits, v))
+
+
+def shoup_constant(w: int, p: int, word_bits: int) -> int:
+    out = _c_u64()
+    rc = load().hntt_shoup_constant(w, p, word_bits, ctypes.byref(out))
+    if rc:
+        raise HnttError(rc, "bad Shoup constant arguments")
+    return int(out.value)
+
+
+def strerror(status: int) -> str:
+    return load().hntt_strerror(status).decode()
+
+
+# ------------------------------------------------------------------------------------------------
+def _word_bits(t: torch.Tensor) -> int:
+    es = t.element_size()
+    if es not in (4, 8) or t.dtype.is_floating_point or t.dtype.is_complex:
+        raise TypeError(f"expected a 32- or 64-bit integer tensor, got {t.dtype}")
+    return es * 8
+
+
+def _stream_handle(stream, device) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Context:
+    """A library context bound to one HIP device (twiddle tables and workspaces live here)."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0):
+        self.lib = load()
+        self.device = device
+        h = _c_vp()
+        rc = self.lib.hntt_create(ctypes.byref(h), device, mem_budget)
+        if rc:
+            raise HnttError(rc, "hntt_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.hntt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self.lib.hntt_last_error(self.handle).decode()
+
+    def _check(self, rc: int):
+        if rc:
+            raise HnttError(rc, self.last_error() or strerror(rc))
+
+    # -- descriptor helpers ----------------------------------------------------------------------
+    @staticmethod
+    def descs(rows: Iterable[torch.Tensor], p: int, omega: int, log2_len: int | None = None):
+        rows = list(rows)
+        arr = (Desc * len(rows))()
+        for i, t in enumerate(rows):
+            wb = _word_bits(t)
+            l = log2_len if log2_len is not None else (t.numel().bit_length() - 1)
+            arr[i] = Desc(p, omega, t.data_ptr(), l, wb)
+        return arr
+
+    @staticmethod
+    def rows_of(x: torch.Tensor) -> list[torch.Tensor]:
+        """Rows of a [batch, L] (or [L]) contiguous tensor as separate transforms."""
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return [x] if x.dim() == 1 else list(x.reshape(-1, x.shape[-1]).unbind(0))
+
+    # -- transforms --------------------------------------------------------------------------------
+    def ntt_forward(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None):
+        """In-place forward NTT of every row of x (natural in, bit-reversed out)."""
+        self._transform(self.lib.hntt_ntt_forward, x, p, omega, plain, normalize, stream)
+        return x
+
+    def ntt_inverse(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None):
+        """In-place inverse NTT of every row of x (bit-reversed in, natural out, times L^-1)."""
+        self._transform(self.lib.hntt_ntt_inverse, x, p, omega, plain, normalize, stream)
+        return x
+
+    def _transform(self, fn, x, p, omega, plain, normalize, stream):
+        rows = self.rows_of(x) if isinstance(x, torch.Tensor) else list(x)
+        arr = self.descs(rows, p, omega)
+        flags = (PLAIN if plain else 0) | (0 if normalize else NO_NORMALIZE)
+        dev = rows[0].device if rows else torch.device("cuda", self.device)
+        self._check(fn(self.handle, arr, len(rows), flags, _stream_handle(stream, dev)))
+
+    def ntt_descs(self, fn_name: str, arr, flags: int = 0, stream=None):
+        """Call hntt_ntt_forward/inverse with a prebuilt descriptor array."""
+        fn = getattr(self.lib, fn_name)
+        self._check(fn(self.handle, arr, len(arr), flags, _stream_handle(stream, torch.device("cuda", self.device))))
+
+    def validate(self, arr, flags: int = 0) -> int:
+        return int(self.lib.hntt_validate(self.handle, arr, len(arr), flags))
+
+    def pointwise_mul(self, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, p: int, stream=None):
+        wb = _word_bits(a)
+        d = (PwDesc * 1)(PwDesc(p, a.data_ptr(), b.data_ptr(), c.data_ptr(), a.numel(), wb, 0))
+        self._check(self.lib.hntt_pointwise_mul(self.handle, d, 1, 0, _stream_handle(stream, a.device)))
+        return c
+
+    def polymul_crt(self, pairs: Sequence[tuple[torch.Tensor, torch.Tensor]], outs: Sequence[torch.Tensor],
+                    plain: bool = False, stream=None):
+        arr = (PolyDesc * len(pairs))()
+        for i, ((a, b), o) in enumerate(zip(pairs, outs)):
+            arr[i] = PolyDesc(a.data_ptr(), b.data_ptr(), o.data_ptr(), a.numel(), b.numel())
+        dev = outs[0].device if outs else torch.device("cuda", self.device)
+        self._check(self.lib.hntt_polymul_crt(self.handle, arr, len(pairs), PLAIN if plain else 0,
+                                              _stream_handle(stream, dev)))
+        return outs
+
+    def debug_butterfly(self, kind: int, p: int, x, y, w, wp, xo, yo, stream=None):
+        wb = _word_bits(x)
+        self._check(self.lib.hntt_debug_butterfly(self.handle, kind, wb, p, x.data_ptr(), y.data_ptr(), w.data_ptr(),
+                                                  wp.data_ptr(), xo.data_ptr(), yo.data_ptr(), x.numel(),
+                                                  _stream_handle(stream, x.device)))

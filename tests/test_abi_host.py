@@ -1,0 +1,140 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol, and its
+host logic (number theory, Shoup constants, descriptor checks) is right."""
+import ctypes
+import os
+import random
+import re
+
+import pytest
+import sympy
+
+from paper_1205_2926_amd import hntt
+from paper_1205_2926_amd.workloads import CRT_PRIMES, P30, P62
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "hntt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hntt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hntt.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(hntt.SIGNATURES), "binding signatures must cover exactly the header"
+
+
+def test_strerror():
+    for s in (0, -1, -2, -3, -4, -5):
+        assert hntt.strerror(s)
+    assert hntt.strerror(-99) == "unknown status"
+
+
+def test_is_prime_matches_sympy():
+    r = random.Random(1)
+    nums = list(range(3000)) + [2047, 1373653, 3215031751, 3825123056546413051, P30, P62, 2**64 - 59]
+    nums += [r.randrange(1 << 64) for _ in range(300)]
+    for n in nums:
+        assert hntt.is_prime(n) == sympy.isprime(n), n
+
+
+def test_primitive_roots_and_roots_of_unity():
+    for p, g in list(CRT_PRIMES) + [(P62, 3), (17, 3), (7681, 17)]:
+        assert hntt.primitive_root(p) == sympy.primitive_root(p) == g
+    # the constants of the small and headline configurations
+    assert hntt.root_of_unity(P30, 10) == 258648936
+    assert hntt.root_of_unity(P30, 20) == 565042129
+    assert hntt.root_of_unity(P62, 22) == 3217870244631358983
+    for p, _ in CRT_PRIMES:
+        for l in (1, 9, 17, 23):
+            w = hntt.root_of_unity(p, l)
+            assert pow(w, 1 << l, p) == 1 and pow(w, 1 << (l - 1), p) == p - 1
+    with pytest.raises(hntt.HnttError):
+        hntt.root_of_unity(P30, 24)
+
+
+def test_find_prime():
+    assert hntt.find_prime(62, 24) == P62
+    assert hntt.find_prime(30, 25) == 0 or sympy.isprime(hntt.find_prime(30, 25))
+    for bits, v in ((20, 8), (31, 20), (40, 30)):
+        c = ((1 << bits) - 2) // (1 << v) * (1 << v) + 1
+        while not sympy.isprime(c):
+            c -= 1 << v
+        assert hntt.find_prime(bits, v) == c
+
+
+def test_shoup_constants_bracket():
+    """W' = floor(W beta / p):  W' p <= W beta < (W' + 1) p  (Algorithm 2 input conditions)."""
+    r = random.Random(2)
+    for p, bits in ((P30, 32), (754974721, 32), (167772161, 32), (P62, 64)):
+        beta = 1 << bits
+        for w in [0, 1, p - 1, p // 2] + [r.randrange(p) for _ in range(200)]:
+            wp = hntt.shoup_constant(w, p, bits)
+            assert wp * p <= w * beta < (wp + 1) * p
+    assert hntt.shoup_constant(258648936, P30, 32) == 1112842479
+    with pytest.raises(hntt.HnttError):
+        hntt.shoup_constant(P30, P30, 32)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = hntt.Context(0)
+    yield c
+    c.close()
+
+
+def _desc(p=P30, omega=258648936, data=4096, l=10, wb=32):
+    return (hntt.Desc * 1)(hntt.Desc(p, omega, data, l, wb))
+
+
+@pytest.mark.parametrize("kw,status,msg", [
+    (dict(data=0), hntt.EINVAL, "NULL"),
+    (dict(data=4098), hntt.EINVAL, "aligned"),
+    (dict(wb=16), hntt.EINVAL, "word_bits"),
+    (dict(l=0), hntt.EINVAL, "log2_len"),
+    (dict(l=31), hntt.EINVAL, "log2_len"),
+    (dict(p=998244351), hntt.EINVAL, "divide"),
+    (dict(p=998244352), hntt.EINVAL, "odd"),
+    (dict(p=1 + 2**30), hntt.EUNSUPPORTED, "2^30"),
+    (dict(omega=3), hntt.EINVAL, "primitive"),
+    (dict(omega=P30), hntt.EINVAL, "omega"),
+    (dict(l=24), hntt.EINVAL, "divide"),
+    (dict(p=12289, omega=pow(11, 3, 12289), l=12), hntt.OK, ""),
+    (dict(p=7681 * 1 + 0, omega=1, l=1), hntt.EINVAL, "primitive"),
+])
+def test_descriptor_checks(ctx, kw, status, msg):
+    arr = _desc(**kw)
+    assert ctx.validate(arr) == status, ctx.last_error()
+    assert msg in ctx.last_error()
+
+
+def test_plain_allows_larger_primes(ctx):
+    # 2013265921 = 15 * 2^27 + 1 < 2^31: legal for Algorithm 2 (p < beta/2), not for Algorithm 3 (p < beta/4)
+    p = 2013265921
+    w = pow(31, (p - 1) >> 10, p)
+    arr = _desc(p=p, omega=w)
+    assert ctx.validate(arr) == hntt.EUNSUPPORTED
+    assert ctx.validate(arr, hntt.PLAIN) == hntt.OK
+
+
+def test_composite_modulus_rejected(ctx):
+    # 3 * 2^30 + 1 = 3221225473 is composite (and above beta/4 anyway), 7 * 2^20 + 1 = 7340033 is prime
+    n = 5 * 7340033  # composite, odd, = 1 mod 2^? small
+    arr = _desc(p=n, omega=1, l=1)
+    assert ctx.validate(arr) == hntt.EINVAL
+
+
+def test_transform_argument_errors_enqueue_nothing(ctx):
+    """Bad descriptors fail on the host before any device call, so this runs without a GPU."""
+    bad = (hntt.Desc * 2)(hntt.Desc(P30, 258648936, 4096, 10, 32), hntt.Desc(P30, 3, 8192, 10, 32))
+    rc = ctx.lib.hntt_ntt_forward(ctx.handle, bad, 2, 0, None)
+    assert rc == hntt.EINVAL and "primitive" in ctx.last_error()
+    rc = ctx.lib.hntt_ntt_inverse(ctx.handle, bad, 2, 0x80, None)
+    assert rc == hntt.EINVAL and "flag" in ctx.last_error()
+    assert ctx.lib.hntt_ntt_forward(ctx.handle, None, 0, 0, None) == hntt.OK
+    assert ctx.lib.hntt_ntt_forward(None, None, 0, 0, None) == hntt.EINVAL

@@ -1,0 +1,277 @@
+"""HIP transforms against the CPU oracle, element by element (bit-exact: this is exact
+integer work, so every fully reduced output must equal the oracle's)."""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1205_2926_amd import hntt
+from paper_1205_2926_amd.workloads import (BATCH8_4M_U64, BATCH64_1M, CRT_PRIMES, G30, G62, P30, P62, SINGLE_1K,
+                                           uniform_residues)
+from tests.gpu_util import dev, host, rev
+from tests.oracle_pins import naive_dft, to_bitrev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = hntt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.Oracle()
+
+
+def _np_dtype(wb):
+    return np.uint32 if wb == 32 else np.uint64
+
+
+def _omega(orc, p, g, l):
+    w = orc.root_of_unity(p, g, l)
+    assert w == hntt.root_of_unity(p, l)
+    return w
+
+
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("plain", [False, True], ids=["lazy", "plain"])
+def test_single_1k(ctx, orc, plain):
+    """One forward NTT of 1024 residues mod 998244353 with omega = 3^((p-1)/1024):
+    bit-exact against the oracle and the naive DFT, output bit-reversed in [0,p)."""
+    cfg = SINGLE_1K
+    x = cfg.data()[0]
+    w = _omega(orc, cfg.p, cfg.g, cfg.log2_len)
+    assert w == 258648936
+    t = dev(x)
+    ctx.ntt_forward(t, cfg.p, w, plain=plain)
+    got = host(t, np.uint32)
+    ref = orc.forward(x, cfg.log2_len, cfg.p, w)
+    np.testing.assert_array_equal(got.astype(np.uint64), ref)
+    assert got.tolist() == to_bitrev(naive_dft(x.tolist(), cfg.p, w))
+    ctx.ntt_inverse(t, cfg.p, w, plain=plain)
+    np.testing.assert_array_equal(host(t, np.uint32), x)
+
+
+LENGTHS_32 = [(l, P30, G30) for l in range(1, 24)] + [(24, 167772161, 3)]
+LENGTHS_64 = [(l, P62, G62) for l in range(1, 23)]
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["lazy", "plain"])
+@pytest.mark.parametrize("wb,l,p,g", [(32, *c) for c in LENGTHS_32] + [(64, *c) for c in LENGTHS_64],
+                         ids=lambda v: str(v))
+def test_every_length(ctx, orc, wb, l, p, g, plain):
+    """Forward and inverse at every length from 2 up to the two-pass limit, several
+    tiles and ragged batch sizes, against the oracle."""
+    batch = 3 if l <= 14 else 1
+    w = _omega(orc, p, g, l)
+    x = uniform_residues(100 + l, (batch, 1 << l), p, _np_dtype(wb))
+    t = dev(x)
+    ctx.ntt_forward(t, p, w, plain=plain)
+    np.testing.assert_array_equal(host(t, _np_dtype(wb)).astype(np.uint64), orc.forward(x, l, p, w))
+    y = uniform_residues(200 + l, (batch, 1 << l), p, _np_dtype(wb))
+    u = dev(y)
+    ctx.ntt_inverse(u, p, w, plain=plain)
+    np.testing.assert_array_equal(host(u, _np_dtype(wb)).astype(np.uint64), orc.inverse(y, l, p, w))
+    ctx.ntt_forward(u, p, w, plain=plain)
+    np.testing.assert_array_equal(host(u, _np_dtype(wb)), y)
+
+
+def _sampled_points(orc, x, got, l, p, w, per_row, seed):
+    r = random.Random(seed)
+    for b in range(x.shape[0]):
+        for j in [0, (1 << l) - 1] + [r.randrange(1 << l) for _ in range(per_row - 2)]:
+            assert int(got[b, rev(j, l)]) == orc.dft_point(x[b], l, p, w, j), (b, j)
+
+
+def test_headline_batch64_lazy_vs_plain(ctx, orc):
+    """64 forward+inverse NTTs of length 2^20 mod 998244353 (the benchmark's workload, same
+    launches): lazy and plain agree bit for bit, whole transforms match the oracle on a
+    subset, every transform matches the definition at sampled outputs, and the round trip
+    returns the input exactly."""
+    cfg = BATCH64_1M
+    x = cfg.data()
+    l, p = cfg.log2_len, cfg.p
+    w = _omega(orc, p, cfg.g, l)
+    assert w == 565042129
+    t_lazy, t_plain = dev(x), dev(x)
+    ctx.ntt_forward(t_lazy, p, w)
+    ctx.ntt_forward(t_plain, p, w, plain=True)
+    got = host(t_lazy, np.uint32)
+    np.testing.assert_array_equal(got, host(t_plain, np.uint32))
+    for b in (0, 17, 63):
+        np.testing.assert_array_equal(got[b].astype(np.uint64), orc.forward(x[b], l, p, w))
+    _sampled_points(orc, x, got, l, p, w, per_row=3, seed=5)
+    ctx.ntt_inverse(t_lazy, p, w)
+    ctx.ntt_inverse(t_plain, p, w, plain=True)
+    np.testing.assert_array_equal(host(t_lazy, np.uint32), x)
+    np.testing.assert_array_equal(host(t_plain, np.uint32), x)
+
+
+def test_u64_batch8(ctx, orc):
+    """8 NTTs of length 2^22 over the 62-bit prime on 64-bit words."""
+    cfg = BATCH8_4M_U64
+    x = cfg.data()
+    l, p = cfg.log2_len, cfg.p
+    w = _omega(orc, p, cfg.g, l)
+    assert w == 3217870244631358983
+    t = dev(x)
+    tp = dev(x)
+    ctx.ntt_forward(t, p, w)
+    ctx.ntt_forward(tp, p, w, plain=True)
+    got = host(t, np.uint64)
+    np.testing.assert_array_equal(got, host(tp, np.uint64))
+    np.testing.assert_array_equal(got[0], orc.forward(x[0], l, p, w))
+    _sampled_points(orc, x, got, l, p, w, per_row=2, seed=6)
+    ctx.ntt_inverse(t, p, w)
+    np.testing.assert_array_equal(host(t, np.uint64), x)
+
+
+def test_mixed_batch_one_call(ctx, orc):
+    """One call with descriptors of different primes, lengths and word sizes."""
+    specs = [(P30, G30, 20, 32), (754974721, 11, 9, 32), (167772161, 3, 13, 32), (P62, G62, 16, 64),
+             (P30, G30, 20, 32), (P62, G62, 3, 64), (167772161, 3, 1, 32)]
+    xs, ts, descs = [], [], (hntt.Desc * len(specs))()
+    for i, (p, g, l, wb) in enumerate(specs):
+        x = uniform_residues(300 + i, 1 << l, p, _np_dtype(wb))
+        t = dev(x)
+        xs.append(x)
+        ts.append(t)
+        descs[i] = hntt.Desc(p, _omega(orc, p, g, l), t.data_ptr(), l, wb)
+    ctx.ntt_descs("hntt_ntt_forward", descs)
+    for (p, g, l, wb), x, t in zip(specs, xs, ts):
+        np.testing.assert_array_equal(host(t, _np_dtype(wb)).astype(np.uint64),
+                                      orc.forward(x, l, p, _omega(orc, p, g, l)))
+
+
+@pytest.mark.parametrize("l", [5, 12, 20])
+def test_closed_forms_and_extremes(ctx, orc, l):
+    p, g = P30, G30
+    L = 1 << l
+    w = _omega(orc, p, g, l)
+    cases = {
+        "zeros": np.zeros(L, np.uint32),
+        "all_p_minus_1": np.full(L, p - 1, np.uint32),
+        "delta0": np.eye(1, L, 0, dtype=np.uint32)[0],
+        "ones": np.ones(L, np.uint32),
+    }
+    for name, x in cases.items():
+        for plain in (False, True):
+            t = dev(x)
+            ctx.ntt_forward(t, p, w, plain=plain)
+            got = host(t, np.uint32)
+            np.testing.assert_array_equal(got.astype(np.uint64), orc.forward(x, l, p, w), err_msg=name)
+            if name == "delta0":
+                assert np.all(got == 1)
+            if name == "ones":
+                assert got[0] == L % p and not np.any(got[1:])
+
+
+def test_lazy_accepts_redundant_inputs(ctx, orc):
+    """Algorithm 3 takes inputs in [0,2p) and Algorithm 4 in [0,4p): redundant
+    representatives give the same fully reduced result."""
+    p, l = P30, 20
+    w = _omega(orc, p, G30, l)
+    x = uniform_residues(7, 1 << l, p, np.uint32)
+    rng = np.random.Generator(np.random.PCG64(8))
+    red = (x.astype(np.uint64) + p * rng.integers(0, 2, size=x.size, dtype=np.uint64)).astype(np.uint32)
+    t = dev(red)
+    ctx.ntt_forward(t, p, w)
+    np.testing.assert_array_equal(host(t, np.uint32).astype(np.uint64), orc.forward(x, l, p, w))
+    red4 = (x.astype(np.uint64) + p * rng.integers(0, 4, size=x.size, dtype=np.uint64)).astype(np.uint32)
+    u = dev(red4)
+    ctx.ntt_inverse(u, p, w)
+    np.testing.assert_array_equal(host(u, np.uint32).astype(np.uint64), orc.inverse(x, l, p, w))
+
+
+@pytest.mark.parametrize("l", [10, 20])
+def test_no_normalize_ranges(ctx, orc, l):
+    """Without the final reduction the lazy forward result lies in [0,2p) and the inverse
+    in [0,4p) (Theorems 2 and 3), congruent to the oracle's."""
+    p = P30
+    w = _omega(orc, p, G30, l)
+    x = uniform_residues(9, 1 << l, p, np.uint32)
+    t = dev(x)
+    ctx.ntt_forward(t, p, w, normalize=False)
+    got = host(t, np.uint32).astype(np.uint64)
+    assert got.max() < 2 * p
+    np.testing.assert_array_equal(got % p, orc.forward(x, l, p, w))
+    u = dev(x)
+    ctx.ntt_inverse(u, p, w, normalize=False)
+    got = host(u, np.uint32).astype(np.uint64)
+    assert got.max() < 4 * p
+    np.testing.assert_array_equal(got % p, orc.inverse(x, l, p, w))
+
+
+def test_deterministic(ctx):
+    p, l = P30, 20
+    w = hntt.root_of_unity(p, l)
+    x = uniform_residues(10, (4, 1 << l), p, np.uint32)
+    a, b = dev(x), dev(x)
+    ctx.ntt_forward(a, p, w)
+    ctx.ntt_forward(b, p, w)
+    assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------------------------------------
+_KIND = {"alg2_plain_fwd": 0, "alg3_lazy_fwd": 1, "alg4_lazy_inv": 2, "plain_inv": 3}
+
+
+@pytest.mark.parametrize("kind", list(_KIND))
+@pytest.mark.parametrize("wb,p", [(32, P30), (32, 167772161), (64, P62)], ids=["p30", "p28", "p62"])
+def test_butterfly_theorems(ctx, kind, wb, p):
+    """Each device butterfly against its algorithm's stated output range and congruences
+    (Theorems 1-3), with exact Python integers, on random and edge operands."""
+    k = _KIND[kind]
+    beta = 1 << wb
+    in_bound = {0: p, 1: 2 * p, 2: 4 * p, 3: p}[k]
+    out_bound = {0: p, 1: 2 * p, 2: 4 * p, 3: p}[k]
+    r = random.Random(k * 7 + wb)
+    g = G62 if wb == 64 else hntt.primitive_root(p)
+    omega = pow(g, (p - 1) >> 10, p)
+    edges = sorted(e for e in {0, 1, p - 1, p, 2 * p - 1, 3 * p, in_bound - 1} if e < in_bound)
+    xs, ys, ws = [], [], []
+    for X in edges:
+        for Y in edges:
+            for W in (1, p - 1, omega):
+                xs.append(X)
+                ys.append(Y)
+                ws.append(W)
+    for _ in range(4000):
+        xs.append(r.randrange(in_bound))
+        ys.append(r.randrange(in_bound))
+        ws.append(r.randrange(1, p))
+    wps = [(W * beta) // p for W in ws]
+    dt = _np_dtype(wb)
+    X, Y, W, WP = (dev(np.array(v, dtype=dt)) for v in (xs, ys, ws, wps))
+    XO, YO = torch.empty_like(X), torch.empty_like(Y)
+    ctx.debug_butterfly(k, p, X, Y, W, WP, XO, YO)
+    xo = host(XO, dt).tolist()
+    yo = host(YO, dt).tolist()
+    for i in range(len(xs)):
+        a, b, w_ = xs[i], ys[i], ws[i]
+        assert 0 <= xo[i] < out_bound and 0 <= yo[i] < out_bound, (kind, a, b, w_, xo[i], yo[i])
+        if k in (0, 1):
+            assert xo[i] % p == (a + b) % p and yo[i] % p == w_ * (a - b) % p, (kind, a, b, w_)
+        else:
+            assert xo[i] % p == (a + w_ * b) % p and yo[i] % p == (a - w_ * b) % p, (kind, a, b, w_)
+
+
+@pytest.mark.parametrize("wb,p", [(32, P30), (32, 754974721), (32, 167772161), (64, P62)])
+def test_pointwise_mul(ctx, orc, wb, p):
+    n = (1 << 18) + 77
+    dt = _np_dtype(wb)
+    a = uniform_residues(11, n, p, dt)
+    b = uniform_residues(12, n, p, dt)
+    a[:3] = [0, p - 1, p - 1]
+    b[:3] = [p - 1, p - 1, 0]
+    ta, tb = dev(a), dev(b)
+    tc = torch.empty_like(ta)
+    ctx.pointwise_mul(ta, tb, tc, p)
+    np.testing.assert_array_equal(host(tc, dt).astype(np.uint64), orc.pointwise(a, b, p))
+    ctx.pointwise_mul(ta, tb, ta, p)  # in place
+    np.testing.assert_array_equal(host(ta, dt).astype(np.uint64), orc.pointwise(a, b, p))
