@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the lazy-butterfly NTT on one MI355X.
+
+Workload: 64 forward + inverse NTTs of length 2^20 over p = 998244353 on 32-bit
+words (omega = 3^((p-1)/2^20)), uniform residues from seed 2, already resident
+in HBM.  One step = the forward transform of the whole batch followed by the
+inverse (so every step starts from the same data).  The same steps are timed
+again with the fully reducing (plain) butterflies under the identical kernel
+schedule.
+
+Reported: butterflies/s (batch * l * L/2 per direction, counted as the paper
+does), the roofline of the dominant kernel (HIP-event durations of the launches
+inside the timed region), the compulsory-byte HBM fraction, the lazy/plain
+ratio, and the CPU oracle timed on a bounded sample on the host cores.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 int32 lanes/clk x 2.4 GHz = 39.3 Tops/s
+# int32 VALU operations per butterfly on gfx950 (Algorithm 3: add, sub+min for the
+# conditional -2p, sub+add for T, mul_hi, 2x mul_lo, sub; Algorithm 2: 12) and per
+# split-twiddle product (mul_hi, 2x mul_lo, sub; plus one min when fully reducing)
+OPS_BFLY = {"lazy": 9, "plain": 12}
+OPS_TWIDDLE = {"lazy": 4, "plain": 5}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=128,
+                    help="transforms (forward + inverse, length 2^20) in the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device copy of known size: 1 GiB read + 1 GiB written per launch, three launches."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": src.numel() * 4, "copy_bytes_written_per_launch": dst.numel() * 4,
+                      "launches": 3}))
+
+
+def pass_units(name: str, batch: int, l: int):
+    """(butterflies, split-twiddle products) in one launch of the named pass over the batch."""
+    n = int(name.rsplit("_n", 1)[1])
+    L = 1 << l
+    bfly = batch * n * (L // 2)
+    tw = batch * L if name.startswith("cols") else 0
+    return bfly, tw
+
+
+def time_steps(ctx, x, p, w, plain, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        ctx.ntt_forward(x, p, w, plain=plain)
+        ctx.ntt_inverse(x, p, w, plain=plain)
+    torch.cuda.synchronize()
+    ctx.trace_reset()
+    ctx.trace(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.ntt_forward(x, p, w, plain=plain)
+        ctx.ntt_inverse(x, p, w, plain=plain)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.trace(False)
+    kernels = ctx.trace_read()
+    return (t1 - t0) / steps, kernels
+
+
+def cpu_baseline(cfg, w, x_np, sample):
+    import numpy as np
+    import oracle
+    orc = oracle.Oracle()
+    cores = min(16, len(os.sched_getaffinity(0)))
+    l, p = cfg.log2_len, cfg.p
+    rows = [x_np[i % x_np.shape[0]].astype(np.uint64) for i in range(sample)]
+
+    def work(a):
+        orc.lib.oracle_ntt_forward(oracle._ptr(a), l, p, w)
+        f = a.copy()
+        orc.lib.oracle_ntt_inverse(oracle._ptr(a), l, p, w)
+        return f
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        fwd = list(ex.map(work, rows))
+    wall = time.perf_counter() - t0
+    bfly = sample * 2 * l * (1 << (l - 1))
+    return {"value": bfly / wall, "unit": "butterflies/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample} of the 64 transforms (length 2^20), forward + inverse, one transform per "
+                      f"thread, {cores} threads, {wall:.2f} s wall", "wall_s": wall}, fwd, rows
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: every transform batch here fits one MI355X and this build has no "
+              "multi-GPU path (independent batches would shard by descriptor with no communication). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_1205_2926_amd import hntt
+    from paper_1205_2926_amd.workloads import BATCH64_1M
+
+    cfg = BATCH64_1M
+    l, p = cfg.log2_len, cfg.p
+    w = hntt.root_of_unity(p, l)
+    x_np = cfg.data()
+    x = torch.from_numpy(x_np.view(np.int32)).cuda()
+    ctx = hntt.Context(0)
+
+    # correctness gate on the benchmark's own launches: the round trip is exact
+    ctx.ntt_forward(x, p, w)
+    fwd0 = x[0].cpu().numpy().view(np.uint32).copy()
+    ctx.ntt_inverse(x, p, w)
+    assert np.array_equal(x.cpu().numpy().view(np.uint32), x_np), "round trip mismatch"
+
+    bfly_step = 2 * cfg.butterflies
+    res = {}
+    for policy in (["lazy"] if args.no_plain else ["lazy", "plain"]):
+        sec, kernels = time_steps(ctx, x, p, w, policy == "plain", args.steps, args.warmup)
+        res[policy] = (sec, kernels)
+    assert np.array_equal(x.cpu().numpy().view(np.uint32), x_np), "data changed across steps"
+
+    sec, kernels = res["lazy"]
+    value = bfly_step / sec
+    # roofline of the dominant kernel (largest total time in the timed region)
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    avg_s = kernels[dom]["total_ms"] / kernels[dom]["launches"] / 1e3
+    bfly, tw = pass_units(dom, cfg.batch, l)
+    bytes_alg = 2 * (cfg.word_bits // 8) * cfg.batch * (1 << l)
+    ops_alg = bfly * OPS_BFLY["lazy"] + tw * OPS_TWIDDLE["lazy"]
+    hbm = {"bound": "hbm", "achieved": bytes_alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    alu = {"bound": "alu", "achieved": ops_alg / avg_s / 1e12, "peak": VALU_PEAK_TOPS, "unit": "Tops/s"}
+    for r in (hbm, alu):
+        r["frac"] = r["achieved"] / r["peak"]
+    roof = dict(max((hbm, alu), key=lambda r: r["frac"]))
+    roof.update({"kernel": dom, "avg_launch_ms": avg_s * 1e3, "traffic": None,
+                 "other": (alu if roof["bound"] == "hbm" else hbm)})
+
+    out = {
+        "metric": "NTT butterflies/s + %HBM roofline (L=2^20x64, 30-bit p), lazy vs plain",
+        "value": value,
+        "unit": "butterflies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic: uniform residues in [0,p) from numpy PCG64 seed 2",
+        "config": {"workload": "64 forward+inverse NTTs, L=2^20, p=998244353, 32-bit words, lazy butterflies",
+                   "batch": cfg.batch, "log2_len": l, "p": p, "omega": w, "word_bits": cfg.word_bits},
+        "roofline": roof,
+        "hbm_frac_compulsory": (2 * bytes_alg) / sec / 1e9 / HBM_PEAK_GBS,
+        "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in kernels.items()},
+    }
+    if "plain" in res:
+        psec, pk = res["plain"]
+        out["plain"] = {"value": bfly_step / psec, "ms_per_step": psec * 1e3,
+                        "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in pk.items()}}
+        out["lazy_over_plain"] = psec / sec
+    if not args.no_cpu_baseline:
+        cb, fwd, rows = cpu_baseline(cfg, w, x_np, args.cpu_sample)
+        assert np.array_equal(fwd[0], fwd0.astype(np.uint64)), "GPU forward differs from the oracle"
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = value / cb["value"]
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

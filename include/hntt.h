@@ -75,7 +75,8 @@ const char *hntt_strerror(int status);
 const char *hntt_last_error(const hntt_ctx *ctx);
 
 /* One transform: `data` is a device array of 2^log2_len words of word_bits
- * bits (32: uint32_t, 64: uint64_t), transformed in place.
+ * bits (32: uint32_t, 64: uint64_t), transformed in place, aligned to 16
+ * bytes (or to its size, if that is smaller).
  *   p        prime, p = 1 (mod 2^log2_len).  Lazy butterflies need p < beta/4
  *            (Algorithm 3 input conditions); HNTT_PLAIN needs p < beta/2
  *            (Algorithm 2 input conditions); beta = 2^word_bits.
@@ -169,6 +170,19 @@ int hntt_shoup_constant(uint64_t w, uint64_t p, uint32_t word_bits, uint64_t *wp
 /* Check descriptors as hntt_ntt_forward would, without touching the device.
  * Returns HNTT_OK or the error the transform call would return. */
 int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (tracing).  While enabled, every kernel the context launches
+ * is bracketed by two HIP events recorded on its launch stream.
+ * hntt_trace_read waits for the pending events and writes, as JSON text,
+ * {"<kernel>": {"launches": n, "total_ms": t}, ...} accumulated since the last
+ * reset into buf (capacity *len bytes); *len receives the size needed.  Kernel
+ * names are <pass>_<fwd|inv>_<lazy|plain>_u<bits>_n<log2 sub-length>.
+ * Errors: EINVAL; ENOMEM when buf is NULL or too small; EDEVICE.
+ * ------------------------------------------------------------------------- */
+int hntt_trace_enable(hntt_ctx *ctx, int enable);
+int hntt_trace_read(hntt_ctx *ctx, char *buf, size_t *len);
+int hntt_trace_reset(hntt_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
  * Device unit test of the butterflies themselves (Algorithms 2, 3, 4).

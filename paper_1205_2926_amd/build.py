@@ -27,16 +27,23 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
-SOURCES = ["ntt_kernels.hip", "hntt_api.cpp", "polymul.cpp"]
+SOURCES = ["ntt_kernels.hip", "hntt_api.cpp", "polymul.cpp",
+           ("ntt_pass.hip", "u32_fwd", ["-DHNTT_WORD=32", "-DHNTT_INVERSE=0"]),
+           ("ntt_pass.hip", "u32_inv", ["-DHNTT_WORD=32", "-DHNTT_INVERSE=1"]),
+           ("ntt_pass.hip", "u64_fwd", ["-DHNTT_WORD=64", "-DHNTT_INVERSE=0"]),
+           ("ntt_pass.hip", "u64_inv", ["-DHNTT_WORD=64", "-DHNTT_INVERSE=1"])]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(spec) -> str:
+    """spec: a source file name, or (source, object tag, extra flags)."""
+    src, tag, extra = (spec, None, []) if isinstance(spec, str) else spec
+    stem = os.path.basename(src) + (f".{tag}" if tag else "")
+    obj = os.path.join(OBJDIR, stem + ".o")
+    cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError(f"hipcc failed on {src}")
+        raise RuntimeError(f"hipcc failed on {stem}")
     return obj
 
 

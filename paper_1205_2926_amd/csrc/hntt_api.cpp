@@ -88,10 +88,15 @@ int check_desc(hntt_ctx *ctx, const hntt_desc &d, uint32_t flags) {
   if (d.word_bits != 32 && d.word_bits != 64)
     return set_error(ctx, HNTT_EINVAL, "word_bits must be 32 or 64 (got %u)", d.word_bits);
   if (!d.data) return set_error(ctx, HNTT_EINVAL, "data pointer is NULL");
-  if (reinterpret_cast<uintptr_t>(d.data) % (d.word_bits / 8))
-    return set_error(ctx, HNTT_EINVAL, "data pointer is not aligned to the word size");
   if (d.log2_len < 1 || d.log2_len > 30)
     return set_error(ctx, HNTT_EINVAL, "log2_len must be in [1, 30] (got %u)", d.log2_len);
+  {
+    // 16-byte vector accesses: data aligned to 16 bytes or to its own size if smaller
+    const uint64_t bytes = (uint64_t)(d.word_bits / 8) << d.log2_len;
+    const uint64_t align = bytes < 16 ? bytes : 16;
+    if (reinterpret_cast<uintptr_t>(d.data) % align)
+      return set_error(ctx, HNTT_EINVAL, "data pointer is not aligned to %llu bytes", (unsigned long long)align);
+  }
   if (d.p < 3 || !(d.p & 1)) return set_error(ctx, HNTT_EINVAL, "p must be an odd prime (got %llu)",
                                               (unsigned long long)d.p);
   const unsigned limit_bits = d.word_bits - (plain ? 1 : 2);  // p < beta/2 (Alg. 2) or beta/4 (Alg. 3, 4)
@@ -119,41 +124,52 @@ Plan make_plan(int l, int word_bits) {
     pl.split = false;
     pl.r = l;
     pl.c = 0;
+    pl.g_cols = pl.g_rows = 1;
     return pl;
   }
   pl.split = true;
   pl.c = (l + 1) / 2;
   pl.r = l - pl.c;
-  // column pass: as many adjacent columns as the 1024-thread and LDS limits allow
-  const int gmax_cols = word_bits == 32 ? 16 : 8;
-  int g = gmax_cols;
-  while (g > 1 && (tpt_of(pl.r) * g > 1024 || g > (1 << pl.c))) g >>= 1;
-  while (g > 1) {
+  auto lds_ok = [&](int n, int g) {
     PassParams pp{};
     pp.word_bits = word_bits;
-    pp.n = pl.r;
+    pp.n = n;
     pp.group = g;
-    if (pass_lds_bytes(pp) && pass_lds_bytes(pp) <= 80 * 1024) break;
-    g >>= 1;
-  }
+    const size_t b = pass_lds_bytes(pp);
+    return pass_split(n, word_bits).kh == 0 || (b && b <= 80 * 1024);
+  };
+  // column pass: adjacent columns per workgroup so that each row segment is 64 bytes
+  int g = word_bits == 32 ? 16 : 8;
+  while (g > 1 && (pass_tpt(pl.r, word_bits) * g > kMaxPassThreads || g > (1 << pl.c) || !lds_ok(pl.r, g))) g >>= 1;
   pl.g_cols = g;
-  int gr = std::max(1, 256 / tpt_of(pl.c));
-  gr = std::min(gr, 1 << pl.r);
+  // row pass: about 256 threads per workgroup
+  int gr = std::max(1, 256 / pass_tpt(pl.c, word_bits));
+  while (gr > 1 && (gr > (1 << pl.r) || !lds_ok(pl.c, gr))) gr >>= 1;
   pl.g_rows = gr;
   return pl;
 }
 
-// Builds omega_N^(sign*j) for j < N/2 with Shoup constants, as words of word_bits bits.
-static void pow_table(uint64_t root, int half, uint64_t p, int bits, std::vector<uint64_t> &w,
-                      std::vector<uint64_t> &wp) {
-  w.resize(half);
-  wp.resize(half);
+// Per-stage ("heap") table for a transform of length N = 2^n with root w_N:
+// entry (1 << b) + k, b < n, k < 2^b, holds the pair (W, W') for
+// W = w_N^(k << (n-1-b)), the twiddle of the stage that pairs position bit b;
+// W' = floor(W beta / p).  Entry 0 is unused.  Stored as interleaved words.
+static void heap_table(uint64_t root, int n, uint64_t p, int bits, std::vector<uint64_t> &out) {
+  const size_t N = (size_t)1 << n;
+  std::vector<uint64_t> pw(N / 2 > 0 ? N / 2 : 1);
   uint64_t x = 1;
-  for (int j = 0; j < half; ++j) {
-    w[j] = x;
-    wp[j] = shoup_constant(x, p, bits);
+  for (size_t j = 0; j < pw.size(); ++j) {
+    pw[j] = x;
     x = mulmod(x, root, p);
   }
+  out.assign(2 * N, 0);
+  out[0] = 1;
+  out[1] = shoup_constant(1, p, bits);
+  for (int b = 0; b < n; ++b)
+    for (size_t k = 0; k < ((size_t)1 << b); ++k) {
+      const uint64_t w = pw[k << (n - 1 - b)];
+      out[2 * (((size_t)1 << b) + k)] = w;
+      out[2 * (((size_t)1 << b) + k) + 1] = shoup_constant(w, p, bits);
+    }
 }
 
 int upload(hntt_ctx *ctx, const std::vector<uint64_t> &src, int bits, const void **out) {
@@ -194,46 +210,42 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const
   const uint64_t linv = powmod(L % p, p - 2, p);
   t.linv = linv;
   t.linv_p = shoup_constant(linv, p, bits);
-  std::vector<uint64_t> w, wp;
+  std::vector<uint64_t> tab;
   int rc;
-  auto table_pair = [&](uint64_t root, int n, const void **dw, const void **dwp) -> int {
-    pow_table(root, (1 << n) >> 1, p, bits, w, wp);
-    int r = upload(ctx, w, bits, dw);
-    if (r) return r;
-    return upload(ctx, wp, bits, dwp);
+  auto table = [&](uint64_t root, int n, const void **dst) -> int {
+    heap_table(root, n, p, bits, tab);
+    return upload(ctx, tab, bits, dst);
   };
   if (!t.plan.split) {
-    if ((rc = table_pair(omega, l, &t.fwd_w, &t.fwd_wp))) return rc;
-    if ((rc = table_pair(omega_inv, l, &t.inv_w, &t.inv_wp))) return rc;
+    if ((rc = table(omega, l, &t.fwd))) return rc;
+    if ((rc = table(omega_inv, l, &t.inv))) return rc;
   } else {
     const int r = t.plan.r, c = t.plan.c;
     const uint64_t R = 1ull << r, C = 1ull << c;
     // column transforms (length R) use omega^C; row transforms (length C) use omega^R
-    if ((rc = table_pair(powmod(omega, C, p), r, &t.fwd_w, &t.fwd_wp))) return rc;
-    if ((rc = table_pair(powmod(omega_inv, C, p), r, &t.inv_w, &t.inv_wp))) return rc;
-    if ((rc = table_pair(powmod(omega, R, p), c, &t.row_fwd_w, &t.row_fwd_wp))) return rc;
-    if ((rc = table_pair(powmod(omega_inv, R, p), c, &t.row_inv_w, &t.row_inv_wp))) return rc;
+    if ((rc = table(powmod(omega, C, p), r, &t.fwd))) return rc;
+    if ((rc = table(powmod(omega_inv, C, p), r, &t.inv))) return rc;
+    if ((rc = table(powmod(omega, R, p), c, &t.row_fwd))) return rc;
+    if ((rc = table(powmod(omega_inv, R, p), c, &t.row_inv))) return rc;
     // split twiddles, laid out like the data: entry (pos, col) = omega^(col * rev_r(pos)),
-    // and for the inverse L^-1 * omega^(-col * rev_r(pos))
-    std::vector<uint64_t> fw(L), fwp(L), iw(L), iwp(L);
+    // and for the inverse L^-1 * omega^(-col * rev_r(pos)); interleaved with their W'
+    std::vector<uint64_t> f(2 * L), iv(2 * L);
     for (uint64_t pos = 0; pos < R; ++pos) {
       const uint64_t s = bitrev((unsigned)pos, r);
       const uint64_t step_f = powmod(omega, s, p), step_i = powmod(omega_inv, s, p);
       uint64_t xf = 1, xi = linv;
       for (uint64_t col = 0; col < C; ++col) {
-        const uint64_t idx = pos * C + col;
-        fw[idx] = xf;
-        fwp[idx] = shoup_constant(xf, p, bits);
-        iw[idx] = xi;
-        iwp[idx] = shoup_constant(xi, p, bits);
+        const uint64_t idx = 2 * (pos * C + col);
+        f[idx] = xf;
+        f[idx + 1] = shoup_constant(xf, p, bits);
+        iv[idx] = xi;
+        iv[idx + 1] = shoup_constant(xi, p, bits);
         xf = mulmod(xf, step_f, p);
         xi = mulmod(xi, step_i, p);
       }
     }
-    if ((rc = upload(ctx, fw, bits, &t.tt_fwd_w))) return rc;
-    if ((rc = upload(ctx, fwp, bits, &t.tt_fwd_wp))) return rc;
-    if ((rc = upload(ctx, iw, bits, &t.tt_inv_w))) return rc;
-    if ((rc = upload(ctx, iwp, bits, &t.tt_inv_wp))) return rc;
+    if ((rc = upload(ctx, f, bits, &t.tt_fwd))) return rc;
+    if ((rc = upload(ctx, iv, bits, &t.tt_inv))) return rc;
   }
   auto ins = ctx->tables.emplace(key, t);
   *out = &ins.first->second;
@@ -248,6 +260,31 @@ int ensure_device(hntt_ctx *ctx) {
   if (ctx->device >= count) return set_error(ctx, HNTT_EINVAL, "device %d does not exist", ctx->device);
   ctx->device_ready = true;
   return HNTT_OK;
+}
+
+std::string pass_name(const PassParams &pp) {
+  const char *kind = pp.kind == PassKind::kWhole ? "whole" : pp.kind == PassKind::kRows ? "rows" : "cols";
+  char buf[96];
+  snprintf(buf, sizeof buf, "%s_%s_%s_u%d_n%d", kind, pp.inverse ? "inv" : "fwd", pp.lazy ? "lazy" : "plain",
+           pp.word_bits, pp.n);
+  return buf;
+}
+
+// Launch one pass; with tracing on, bracket it with HIP events on the launch stream.
+hipError_t launch_traced(hntt_ctx *ctx, const PassParams &pp, const BatchPtrs &bp, hipStream_t stream) {
+  if (!ctx->trace) return launch_pass(pp, bp, stream);
+  TraceEvent ev{pass_name(pp), nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev.start);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventCreate(&ev.stop)) != hipSuccess) {
+    (void)hipEventDestroy(ev.start);
+    return e;
+  }
+  (void)hipEventRecord(ev.start, stream);
+  e = launch_pass(pp, bp, stream);
+  (void)hipEventRecord(ev.stop, stream);
+  ctx->trace_pending.push_back(ev);
+  return e;
 }
 
 // Run every pass of one transform direction over a batch sharing (p, omega, l, word_bits).
@@ -272,11 +309,10 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const std::vector<void *> &ptr
       pp.log_other = 0;
       pp.group = 1;
       pp.normalize = norm;
-      pp.tw_w = inverse ? t.inv_w : t.fwd_w;
-      pp.tw_wp = inverse ? t.inv_wp : t.fwd_wp;
+      pp.tw = inverse ? t.inv : t.fwd;
       pp.scale_w = t.linv;
       pp.scale_wp = t.linv_p;
-      if ((e = launch_pass(pp, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(whole)");
+      if ((e = launch_traced(ctx, pp, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(whole)");
       continue;
     }
     PassParams cols = pp, rows = pp;
@@ -284,26 +320,23 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const std::vector<void *> &ptr
     cols.n = t.plan.r;
     cols.log_other = t.plan.c;
     cols.group = t.plan.g_cols;
-    cols.tw_w = inverse ? t.inv_w : t.fwd_w;
-    cols.tw_wp = inverse ? t.inv_wp : t.fwd_wp;
-    cols.tt_w = inverse ? t.tt_inv_w : t.tt_fwd_w;
-    cols.tt_wp = inverse ? t.tt_inv_wp : t.tt_fwd_wp;
+    cols.tw = inverse ? t.inv : t.fwd;
+    cols.tt = inverse ? t.tt_inv : t.tt_fwd;
     rows.kind = PassKind::kRows;
     rows.n = t.plan.c;
     rows.log_other = t.plan.r;
     rows.group = t.plan.g_rows;
-    rows.tw_w = inverse ? t.row_inv_w : t.row_fwd_w;
-    rows.tw_wp = inverse ? t.row_inv_wp : t.row_fwd_wp;
+    rows.tw = inverse ? t.row_inv : t.row_fwd;
     if (!inverse) {
       cols.normalize = false;
       rows.normalize = norm;
-      if ((e = launch_pass(cols, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(cols)");
-      if ((e = launch_pass(rows, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(rows)");
+      if ((e = launch_traced(ctx, cols, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(cols)");
+      if ((e = launch_traced(ctx, rows, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(rows)");
     } else {
       rows.normalize = false;
       cols.normalize = norm;
-      if ((e = launch_pass(rows, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(rows)");
-      if ((e = launch_pass(cols, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(cols)");
+      if ((e = launch_traced(ctx, rows, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(rows)");
+      if ((e = launch_traced(ctx, cols, bp, stream)) != hipSuccess) return hip_status(ctx, e, "launch(cols)");
     }
   }
   return HNTT_OK;
@@ -420,6 +453,58 @@ int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint3
     if (e != hipSuccess) return hip_status(ctx, e, "launch(pointwise)");
   }
   return HNTT_OK;
+}
+
+int hntt_trace_enable(hntt_ctx *ctx, int enable) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->trace = enable != 0;
+  return HNTT_OK;
+}
+
+int hntt_trace_reset(hntt_ctx *ctx) {
+  if (!ctx) return HNTT_EINVAL;
+  for (auto &ev : ctx->trace_pending) {
+    (void)hipEventSynchronize(ev.stop);
+    (void)hipEventDestroy(ev.start);
+    (void)hipEventDestroy(ev.stop);
+  }
+  ctx->trace_pending.clear();
+  ctx->trace_acc.clear();
+  return HNTT_OK;
+}
+
+int hntt_trace_read(hntt_ctx *ctx, char *buf, size_t *len) {
+  if (!ctx || !len) return HNTT_EINVAL;
+  int status = HNTT_OK;
+  for (auto &ev : ctx->trace_pending) {
+    float ms = 0;
+    if (hipEventSynchronize(ev.stop) != hipSuccess || hipEventElapsedTime(&ms, ev.start, ev.stop) != hipSuccess)
+      status = set_error(ctx, HNTT_EDEVICE, "trace event failed");
+    TraceAcc &a = ctx->trace_acc[ev.name];
+    a.launches += 1;
+    a.total_ms += ms;
+    (void)hipEventDestroy(ev.start);
+    (void)hipEventDestroy(ev.stop);
+  }
+  ctx->trace_pending.clear();
+  std::string json = "{";
+  bool first = true;
+  for (auto &kv : ctx->trace_acc) {
+    char item[256];
+    snprintf(item, sizeof item, "%s\"%s\": {\"launches\": %llu, \"total_ms\": %.6f}", first ? "" : ", ",
+             kv.first.c_str(), (unsigned long long)kv.second.launches, kv.second.total_ms);
+    json += item;
+    first = false;
+  }
+  json += "}";
+  const size_t need = json.size() + 1;
+  if (!buf || *len < need) {
+    *len = need;
+    return status ? status : HNTT_ENOMEM;
+  }
+  memcpy(buf, json.c_str(), need);
+  *len = need;
+  return status;
 }
 
 int hntt_is_prime(uint64_t n) { return is_prime_u64(n) ? 1 : 0; }

@@ -1,6 +1,7 @@
 // Internal state of a library context (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <map>
@@ -31,15 +32,27 @@ struct Plan {
   int g_rows;  // rows per workgroup in the row pass
 };
 
-// Device twiddle tables for one (p, omega, l, word_bits).
+// Device twiddle tables for one (p, omega, l, word_bits), each an array of
+// interleaved (W, W') pairs.
 struct Tables {
   Plan plan;
-  uint64_t linv, linv_p;  // L^-1 mod p and its Shoup constant
-  const void *fwd_w, *fwd_wp, *inv_w, *inv_wp;                       // whole or column transform
-  const void *row_fwd_w, *row_fwd_wp, *row_inv_w, *row_inv_wp;       // row transform (split)
-  const void *tt_fwd_w, *tt_fwd_wp, *tt_inv_w, *tt_inv_wp;           // split twiddles (split)
+  uint64_t linv, linv_p;                 // L^-1 mod p and its Shoup constant
+  const void *fwd, *inv;                 // whole transform, or the column transform
+  const void *row_fwd, *row_inv;         // row transform (split)
+  const void *tt_fwd, *tt_inv;           // split twiddles (split)
 };
 
+}  // namespace hntt
+
+namespace hntt {
+struct TraceEvent {
+  std::string name;
+  hipEvent_t start, stop;
+};
+struct TraceAcc {
+  uint64_t launches = 0;
+  double total_ms = 0;
+};
 }  // namespace hntt
 
 struct hntt_ctx {
@@ -51,7 +64,17 @@ struct hntt_ctx {
   std::map<uint64_t, bool> prime_cache;
   std::map<std::tuple<uint64_t, uint64_t, int, int>, hntt::Tables> tables;
   std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
-  void release_device_state() { tables.clear(); }
+  bool trace = false;
+  std::vector<hntt::TraceEvent> trace_pending;
+  std::map<std::string, hntt::TraceAcc> trace_acc;
+  void release_device_state() {
+    tables.clear();
+    for (auto &ev : trace_pending) {
+      (void)hipEventDestroy(ev.start);
+      (void)hipEventDestroy(ev.stop);
+    }
+    trace_pending.clear();
+  }
 };
 
 namespace hntt {
@@ -59,5 +82,9 @@ int check_desc(hntt_ctx *ctx, const hntt_desc &d, uint32_t flags);
 Plan make_plan(int l, int word_bits);
 int ensure_device(hntt_ctx *ctx);
 int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const Tables **out);
+// Launch wrapper that records HIP events around the launch when tracing is on.
+struct PassParams;
+hipError_t traced(hntt_ctx *ctx, const std::string &name, hipStream_t stream, hipError_t (*fn)(const void *, hipStream_t),
+                  const void *arg);
 int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream, bool inverse);
 }  // namespace hntt

@@ -1,4 +1,5 @@
-// NTT pass kernels for gfx950.
+// Pass dispatch, the butterfly unit-test kernel and the pointwise product.
+// The pass kernels themselves are in ntt_pass.hip.
 //
 // A transform of length L = 2^l is computed in at most two passes over HBM.
 // Each pass stages a tile in LDS and runs several radix-2 stages of
@@ -23,307 +24,6 @@
 namespace hntt {
 
 namespace {
-
-constexpr int kRadix = 4;  // stages per register round
-
-// Element `pos` of sub-transform `g` in LDS.
-struct RowLayout {
-  int stride;
-  __device__ __forceinline__ int operator()(int g, int pos) const { return g * stride + pos; }
-};
-struct ColLayout {
-  int G;
-  __device__ __forceinline__ int operator()(int g, int pos) const { return pos * G + g; }
-};
-
-template <class Wd, bool Lazy>
-__device__ __forceinline__ void bfly_fwd(typename Wd::T &x, typename Wd::T &y, typename Wd::T w,
-                                         typename Wd::T wp, typename Wd::T p, typename Wd::T p2) {
-  if constexpr (Lazy) bfly_fwd_lazy<Wd>(x, y, w, wp, p, p2);
-  else bfly_fwd_plain<Wd>(x, y, w, wp, p);
-}
-template <class Wd, bool Lazy>
-__device__ __forceinline__ void bfly_fwd_w1(typename Wd::T &x, typename Wd::T &y, typename Wd::T p,
-                                            typename Wd::T p2) {
-  if constexpr (Lazy) bfly_fwd_lazy_w1<Wd>(x, y, p2);
-  else bfly_fwd_plain_w1<Wd>(x, y, p);
-}
-template <class Wd, bool Lazy>
-__device__ __forceinline__ void bfly_inv(typename Wd::T &x, typename Wd::T &y, typename Wd::T w,
-                                         typename Wd::T wp, typename Wd::T p, typename Wd::T p2) {
-  if constexpr (Lazy) bfly_inv_lazy<Wd>(x, y, w, wp, p, p2);
-  else bfly_inv_plain<Wd>(x, y, w, wp, p);
-}
-template <class Wd, bool Lazy>
-__device__ __forceinline__ void bfly_inv_w1(typename Wd::T &x, typename Wd::T &y, typename Wd::T p,
-                                            typename Wd::T p2) {
-  if constexpr (Lazy) bfly_inv_lazy_w1<Wd>(x, y, p2);
-  else bfly_inv_plain_w1<Wd>(x, y, p);
-}
-
-// One register round of K forward (DIF) stages on the bits [b_lo, b_lo + K) of
-// the position.  Stage i of Algorithm 1 pairs bit b = n - i with twiddle
-// zeta_i^(pos mod 2^b) = omega_N^((pos mod 2^b) << (i - 1)).
-template <class Wd, bool Lazy, int K, class Layout>
-__device__ __forceinline__ void fwd_round(typename Wd::T *lds, Layout lay, int n, int b_lo, int g, int t, int tpt,
-                                          const typename Wd::T *tw, const typename Wd::T *twp, typename Wd::T p,
-                                          typename Wd::T p2) {
-  using T = typename Wd::T;
-  const int groups = 1 << (n - K);
-  for (int gi = t; gi < groups; gi += tpt) {
-    const int low = gi & ((1 << b_lo) - 1);
-    const int base = ((gi >> b_lo) << (b_lo + K)) | low;
-    T v[1 << K];
-#pragma unroll
-    for (int e = 0; e < (1 << K); ++e) v[e] = lds[lay(g, base | (e << b_lo))];
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-      const int hb = K - 1 - s;
-      const int b = b_lo + hb;
-      if (b == 0) {
-#pragma unroll
-        for (int e = 0; e < (1 << K); ++e)
-          if (!(e & (1 << hb))) bfly_fwd_w1<Wd, Lazy>(v[e], v[e | (1 << hb)], p, p2);
-      } else {
-        const int shift = n - 1 - b;
-#pragma unroll
-        for (int e = 0; e < (1 << K); ++e)
-          if (!(e & (1 << hb))) {
-            const int pos = base | (e << b_lo);
-            const int idx = (pos & ((1 << b) - 1)) << shift;
-            bfly_fwd<Wd, Lazy>(v[e], v[e | (1 << hb)], tw[idx], twp[idx], p, p2);
-          }
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < (1 << K); ++e) lds[lay(g, base | (e << b_lo))] = v[e];
-  }
-}
-
-// One register round of K inverse stages (Algorithm 1 run backwards): bits
-// b_lo upward, butterfly (X + W Y, X - W Y) with W = omega_N^(-(pos mod 2^b) << (i-1)).
-template <class Wd, bool Lazy, int K, class Layout>
-__device__ __forceinline__ void inv_round(typename Wd::T *lds, Layout lay, int n, int b_lo, int g, int t, int tpt,
-                                          const typename Wd::T *tw, const typename Wd::T *twp, typename Wd::T p,
-                                          typename Wd::T p2) {
-  using T = typename Wd::T;
-  const int groups = 1 << (n - K);
-  for (int gi = t; gi < groups; gi += tpt) {
-    const int low = gi & ((1 << b_lo) - 1);
-    const int base = ((gi >> b_lo) << (b_lo + K)) | low;
-    T v[1 << K];
-#pragma unroll
-    for (int e = 0; e < (1 << K); ++e) v[e] = lds[lay(g, base | (e << b_lo))];
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-      const int hb = s;
-      const int b = b_lo + hb;
-      if (b == 0) {
-#pragma unroll
-        for (int e = 0; e < (1 << K); ++e)
-          if (!(e & (1 << hb))) bfly_inv_w1<Wd, Lazy>(v[e], v[e | (1 << hb)], p, p2);
-      } else {
-        const int shift = n - 1 - b;
-#pragma unroll
-        for (int e = 0; e < (1 << K); ++e)
-          if (!(e & (1 << hb))) {
-            const int pos = base | (e << b_lo);
-            const int idx = (pos & ((1 << b) - 1)) << shift;
-            bfly_inv<Wd, Lazy>(v[e], v[e | (1 << hb)], tw[idx], twp[idx], p, p2);
-          }
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < (1 << K); ++e) lds[lay(g, base | (e << b_lo))] = v[e];
-  }
-}
-
-// All n stages of a length-2^n sub-transform held in LDS.  Rounds of kRadix
-// stages; the remainder round takes the innermost bits.
-template <class Wd, bool Lazy, bool Inverse, class Layout>
-__device__ void sub_transform(typename Wd::T *lds, Layout lay, int n, int g, int t, int tpt, const typename Wd::T *tw,
-                              const typename Wd::T *twp, typename Wd::T p) {
-  using T = typename Wd::T;
-  const T p2 = p + p;
-  const int nr = (n + kRadix - 1) / kRadix;
-  const int rem = n - kRadix * (nr - 1);
-  for (int r = 0; r < nr; ++r) {
-    // forward: round r covers bits [n - 4(r+1), n - 4r) except the last (rem bits at 0);
-    // inverse: the same rounds in reverse order.
-    const int rr = Inverse ? (nr - 1 - r) : r;
-    const bool last = (rr == nr - 1);
-    const int b_lo = last ? 0 : n - kRadix * (rr + 1);
-    const int k = last ? rem : kRadix;
-    if constexpr (Inverse) {
-      switch (k) {
-        case 1: inv_round<Wd, Lazy, 1>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-        case 2: inv_round<Wd, Lazy, 2>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-        case 3: inv_round<Wd, Lazy, 3>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-        default: inv_round<Wd, Lazy, 4>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-      }
-    } else {
-      switch (k) {
-        case 1: fwd_round<Wd, Lazy, 1>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-        case 2: fwd_round<Wd, Lazy, 2>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-        case 3: fwd_round<Wd, Lazy, 3>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-        default: fwd_round<Wd, Lazy, 4>(lds, lay, n, b_lo, g, t, tpt, tw, twp, p, p2); break;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-template <class T>
-__device__ __forceinline__ void stage_table(T *dst_w, T *dst_wp, const T *src_w, const T *src_wp, int count) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) {
-    dst_w[i] = src_w[i];
-    dst_wp[i] = src_wp[i];
-  }
-}
-
-// Final reduction of a lazy result: forward outputs lie in [0,2p), inverse in [0,4p).
-template <class Wd, bool Lazy, bool Inverse>
-__device__ __forceinline__ typename Wd::T normalize(typename Wd::T x, typename Wd::T p) {
-  using T = typename Wd::T;
-  if constexpr (!Lazy) return x;
-  if constexpr (Inverse) x = csub<T>(x, p + p);
-  return csub<T>(x, p);
-}
-
-// ---------------------------------------------------------------------------------------------
-// kWhole and kRows: each workgroup owns `group` contiguous rows of length 2^n
-// (kWhole: one whole transform per row, log_other = 0).
-template <class Wd, bool Lazy, bool Inverse>
-__global__ void __launch_bounds__(1024) k_rows(BatchPtrs ptrs, int n, int log_rows, int group, uint64_t p64,
-                                               const typename Wd::T *__restrict__ tw_g,
-                                               const typename Wd::T *__restrict__ twp_g, int normalize_out,
-                                               uint64_t scale_w64, uint64_t scale_wp64) {
-  using T = typename Wd::T;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const T p = (T)p64;
-  const int N = 1 << n;
-  const int half = N >> 1;
-  T *tw = reinterpret_cast<T *>(smem_raw);
-  T *twp = tw + half;
-  T *data = twp + half;
-
-  const int groups_per_transform = (1 << log_rows) / group;
-  const int b = blockIdx.x / groups_per_transform;
-  const int rg = blockIdx.x % groups_per_transform;
-  T *gdata = reinterpret_cast<T *>(ptrs.ptr[b]) + ((size_t)rg * group << n);
-
-  stage_table<T>(tw, twp, tw_g, twp_g, half);
-  const int total = group << n;
-  for (int i = threadIdx.x; i < total; i += blockDim.x) data[i] = gdata[i];
-  __syncthreads();
-
-  const int tpt = blockDim.x / group;
-  const int g = threadIdx.x / tpt;
-  const int t = threadIdx.x % tpt;
-  sub_transform<Wd, Lazy, Inverse>(data, RowLayout{N}, n, g, t, tpt, tw, twp, p);
-
-  const bool scale = Inverse && log_rows == 0;  // whole inverse transform: times L^-1
-  const T sw = (T)scale_w64, swp = (T)scale_wp64;
-  for (int i = threadIdx.x; i < total; i += blockDim.x) {
-    T x = data[i];
-    if (scale) {
-      x = shoup_lazy<Wd>(x, sw, swp, p);  // any x < beta -> [0,2p)
-      x = csub<T>(x, p);
-    } else if (normalize_out) {
-      x = normalize<Wd, Lazy, Inverse>(x, p);
-    }
-    gdata[i] = x;
-  }
-}
-
-// kCols: each workgroup owns `group` adjacent columns of the R x C view
-// (R = 2^n rows, C = 2^log_cols columns).
-template <class Wd, bool Lazy, bool Inverse>
-__global__ void __launch_bounds__(1024) k_cols(BatchPtrs ptrs, int n, int log_cols, int group, uint64_t p64,
-                                               const typename Wd::T *__restrict__ tw_g,
-                                               const typename Wd::T *__restrict__ twp_g,
-                                               const typename Wd::T *__restrict__ tt_w,
-                                               const typename Wd::T *__restrict__ tt_wp, int normalize_out) {
-  using T = typename Wd::T;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const T p = (T)p64;
-  const int R = 1 << n;
-  const int half = R >> 1;
-  const size_t C = (size_t)1 << log_cols;
-  T *tw = reinterpret_cast<T *>(smem_raw);
-  T *twp = tw + half;
-  T *data = twp + half;
-
-  const int groups_per_transform = (int)(C / group);
-  const int b = blockIdx.x / groups_per_transform;
-  const int c0 = (blockIdx.x % groups_per_transform) * group;
-  T *gdata = reinterpret_cast<T *>(ptrs.ptr[b]);
-
-  stage_table<T>(tw, twp, tw_g, twp_g, half);
-  const int total = group << n;
-  for (int i = threadIdx.x; i < total; i += blockDim.x) {
-    const int row = i / group, col = i % group;
-    const size_t gi = (size_t)row * C + c0 + col;
-    T x = gdata[gi];
-    if constexpr (Inverse) {
-      // split twiddle conj(omega)^(col*s) * L^-1 before the column transform
-      x = shoup_lazy<Wd>(x, tt_w[gi], tt_wp[gi], p);
-      if constexpr (!Lazy) x = csub<T>(x, p);
-    }
-    data[i] = x;
-  }
-  __syncthreads();
-
-  const int tpt = blockDim.x / group;
-  const int g = threadIdx.x % group;
-  const int t = threadIdx.x / group;
-  sub_transform<Wd, Lazy, Inverse>(data, ColLayout{group}, n, g, t, tpt, tw, twp, p);
-
-  for (int i = threadIdx.x; i < total; i += blockDim.x) {
-    const int row = i / group, col = i % group;
-    const size_t gi = (size_t)row * C + c0 + col;
-    T x = data[i];
-    if constexpr (!Inverse) {
-      // split twiddle omega^(col*s) after the column transform
-      x = shoup_lazy<Wd>(x, tt_w[gi], tt_wp[gi], p);
-      if constexpr (!Lazy) x = csub<T>(x, p);
-    } else if (normalize_out) {
-      x = normalize<Wd, Lazy, true>(x, p);
-    }
-    gdata[gi] = x;
-  }
-}
-
-template <class Wd, bool Lazy, bool Inverse>
-hipError_t launch_typed(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream) {
-  using T = typename Wd::T;
-  const int tpt = pp.n > kRadix ? (1 << (pp.n - kRadix)) : 1;
-  const int threads = tpt * pp.group;
-  const size_t lds = pass_lds_bytes(pp);
-  if (threads > 1024 || lds == 0) return hipErrorInvalidValue;
-  const T *tw = static_cast<const T *>(pp.tw_w);
-  const T *twp = static_cast<const T *>(pp.tw_wp);
-  static bool attr_set = false;  // allow the full 160 KiB of LDS once per instantiation
-  if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cols<Wd, Lazy, Inverse>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows<Wd, Lazy, Inverse>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
-  if (pp.kind == PassKind::kCols) {
-    const int blocks = ((1 << pp.log_other) / pp.group) * pp.nbatch;
-    hipLaunchKernelGGL((k_cols<Wd, Lazy, Inverse>), dim3(blocks), dim3(threads), lds, stream, ptrs, pp.n,
-                       pp.log_other, pp.group, pp.p, tw, twp, static_cast<const T *>(pp.tt_w),
-                       static_cast<const T *>(pp.tt_wp), (int)pp.normalize);
-  } else {
-    const int log_rows = pp.kind == PassKind::kWhole ? 0 : pp.log_other;
-    const int blocks = ((1 << log_rows) / pp.group) * pp.nbatch;
-    hipLaunchKernelGGL((k_rows<Wd, Lazy, Inverse>), dim3(blocks), dim3(threads), lds, stream, ptrs, pp.n, log_rows,
-                       pp.group, pp.p, tw, twp, (int)pp.normalize, pp.scale_w, pp.scale_wp);
-  }
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------------------------
 template <class Wd>
@@ -381,23 +81,18 @@ T inv_mod_pow2(T p) {  // p^-1 mod 2^bits for odd p, by Newton iteration
 }  // namespace
 
 size_t pass_lds_bytes(const PassParams &pp) {
+  if (pass_split(pp.n, pp.word_bits).kh == 0) return 0;
   const size_t wb = pp.word_bits / 8;
   const size_t N = (size_t)1 << pp.n;
-  const size_t bytes = wb * (N + N * pp.group);  // twiddle table (N/2 pairs) + tile
+  // per-stage twiddle table (N pairs) + padded tile (see LdsIO in ntt_pass.hip)
+  const size_t padded = pp.kind == PassKind::kCols ? N + N / 32 : N + (N >= 32 ? N / 8 : 0);
+  const size_t bytes = wb * (2 * N + padded * pp.group);
   return bytes <= 160 * 1024 ? bytes : 0;
 }
 
 hipError_t launch_pass(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream) {
-  if (pp.word_bits == 32) {
-    if (pp.lazy) return pp.inverse ? launch_typed<Word32, true, true>(pp, ptrs, stream)
-                                   : launch_typed<Word32, true, false>(pp, ptrs, stream);
-    return pp.inverse ? launch_typed<Word32, false, true>(pp, ptrs, stream)
-                      : launch_typed<Word32, false, false>(pp, ptrs, stream);
-  }
-  if (pp.lazy) return pp.inverse ? launch_typed<Word64, true, true>(pp, ptrs, stream)
-                                 : launch_typed<Word64, true, false>(pp, ptrs, stream);
-  return pp.inverse ? launch_typed<Word64, false, true>(pp, ptrs, stream)
-                    : launch_typed<Word64, false, false>(pp, ptrs, stream);
+  if (pp.word_bits == 32) return pp.inverse ? launch_pass_u32_inv(pp, ptrs, stream) : launch_pass_u32_fwd(pp, ptrs, stream);
+  return pp.inverse ? launch_pass_u64_inv(pp, ptrs, stream) : launch_pass_u64_fwd(pp, ptrs, stream);
 }
 
 hipError_t launch_debug_butterfly(int kind, int word_bits, uint64_t p, const void *x, const void *y, const void *w,

@@ -20,6 +20,35 @@ enum class PassKind : int {
   kCols = 2,   // strided columns of length 2^n (outermost stages) plus the split twiddle
 };
 
+constexpr int kMaxPassLog = 12;      // longest sub-transform inside one workgroup: 2^12 words
+constexpr int kMaxPassThreads = 512; // workgroup size limit of the pass kernels (keeps 256 VGPRs available)
+
+// Register rounds of a sub-transform of 2^n words: bits of the high, middle and
+// low rounds (KH + KM + KL = n; KH = 0 means a single round of n bits, KM = 0
+// two rounds).  A thread holds 2^K words of a round in registers; 64-bit words
+// use smaller rounds to stay within the register file.
+struct RoundSplit {
+  int kh, km, kl;
+};
+inline RoundSplit pass_split(int n, int word_bits) {
+  if (word_bits == 32) {
+    if (n <= 6) return {0, 0, n};
+    if (n <= 11) return {(n + 1) / 2, 0, n / 2};
+    return {4, 4, n - 8};
+  }
+  if (n <= 5) return {0, 0, n};
+  if (n <= 8) return {(n + 1) / 2, 0, n / 2};
+  if (n == 9) return {3, 3, 3};
+  if (n == 10) return {4, 3, 3};
+  return {4, 4, n - 8};
+}
+// Threads per sub-transform: one group of the largest round each.
+inline int pass_tpt(int n, int word_bits) {
+  const RoundSplit r = pass_split(n, word_bits);
+  const int kmax = r.kh > r.kl ? (r.kh > r.km ? r.kh : r.km) : (r.kl > r.km ? r.kl : r.km);
+  return 1 << (n - kmax);
+}
+
 struct PassParams {
   PassKind kind;
   int word_bits;   // 32 or 64
@@ -31,13 +60,16 @@ struct PassParams {
   int group;       // sub-transforms per workgroup
   int nbatch;      // transforms in this launch (<= kMaxBatchPerLaunch)
   uint64_t p;
-  const void *tw_w;   // table of omega_N^(+-j), j < 2^(n-1)
-  const void *tw_wp;  // Shoup constants of tw_w
-  const void *tt_w;   // kCols: split twiddles, same shape as the data
-  const void *tt_wp;
+  const void *tw;     // interleaved (W, W') pairs of omega_N^(+-j), j < 2^(n-1)
+  const void *tt;     // kCols: interleaved split twiddles, same shape as the data
   uint64_t scale_w;   // kWhole inverse: L^-1 and its Shoup constant
   uint64_t scale_wp;
 };
+
+hipError_t launch_pass_u32_fwd(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream);
+hipError_t launch_pass_u32_inv(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream);
+hipError_t launch_pass_u64_fwd(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream);
+hipError_t launch_pass_u64_inv(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream);
 
 // Enqueue one pass over `ptrs` on `stream`.  Returns a hipError_t.
 hipError_t launch_pass(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream);

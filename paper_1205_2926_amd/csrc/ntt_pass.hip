@@ -1,0 +1,425 @@
+// One NTT pass kernel family, compiled once per (word size, direction):
+// HNTT_WORD = 32 | 64, HNTT_INVERSE = 0 | 1.
+//
+// A workgroup owns G sub-transforms of length N = 2^n (n = KH + KL):
+//   rows  G contiguous rows of a transform viewed as (#rows x N)   (also whole
+//         transforms: one row, #rows = 1)
+//   cols  G adjacent columns of a transform viewed as (N x #cols), row-major.
+// The n radix-2 stages of Algorithm 1 (Section 1) run in two register rounds:
+// the "high" round pairs position bits [KL, n) and the "low" round bits
+// [0, KL).  A thread keeps the 2^K elements of one group in registers for all
+// K stages of a round, so the tile crosses LDS once per pass:
+//   forward (DIF):  HBM -> high round -> LDS -> low round -> HBM
+//   inverse (DIT):  HBM -> low round  -> LDS -> high round -> HBM
+// With KH = 0 there is one round and no LDS tile at all.  Global loads and
+// stores are issued directly by the rounds that touch HBM; lanes are laid out
+// so that each memory instruction covers contiguous words (columns fastest in
+// a cols pass, positions fastest in a rows pass).
+//
+// Twiddles of the high round depend on the thread's low position bits and are
+// read from an LDS copy of the table; twiddles of the low round are uniform
+// across the workgroup (their indices are compile-time multiples of
+// 2^(n-1-b)), so they come straight from global memory through scalar loads,
+// and the butterflies whose twiddle is 1 skip the product entirely.
+#include "modarith.hpp"
+#include "ntt_kernels.hpp"
+
+#ifndef HNTT_WORD
+#error "HNTT_WORD must be 32 or 64"
+#endif
+#ifndef HNTT_INVERSE
+#error "HNTT_INVERSE must be 0 or 1"
+#endif
+
+#if HNTT_WORD == 32 && HNTT_INVERSE == 0
+#define HNTT_NS pass_u32_fwd
+#elif HNTT_WORD == 32
+#define HNTT_NS pass_u32_inv
+#elif HNTT_INVERSE == 0
+#define HNTT_NS pass_u64_fwd
+#else
+#define HNTT_NS pass_u64_inv
+#endif
+
+namespace hntt {
+namespace HNTT_NS {
+
+#if HNTT_WORD == 32
+using Wd = Word32;
+#else
+using Wd = Word64;
+#endif
+using T = typename Wd::T;
+constexpr bool kInverse = HNTT_INVERSE != 0;
+
+struct alignas(2 * sizeof(T)) Tw2 {
+  T w, wp;
+};
+
+template <bool Lazy>
+__device__ __forceinline__ void bfly(T &x, T &y, T w, T wp, T p, T p2) {
+  if constexpr (kInverse) {
+    if constexpr (Lazy) bfly_inv_lazy<Wd>(x, y, w, wp, p, p2);
+    else bfly_inv_plain<Wd>(x, y, w, wp, p);
+  } else {
+    if constexpr (Lazy) bfly_fwd_lazy<Wd>(x, y, w, wp, p, p2);
+    else bfly_fwd_plain<Wd>(x, y, w, wp, p);
+  }
+}
+
+template <bool Lazy>
+__device__ __forceinline__ void bfly_w1(T &x, T &y, T p, T p2) {
+  if constexpr (kInverse) {
+    if constexpr (Lazy) bfly_inv_lazy_w1<Wd>(x, y, p2);
+    else bfly_inv_plain_w1<Wd>(x, y, p);
+  } else {
+    if constexpr (Lazy) bfly_fwd_lazy_w1<Wd>(x, y, p2);
+    else bfly_fwd_plain_w1<Wd>(x, y, p);
+  }
+}
+
+// Words per 16-byte vector access.
+constexpr int kVec = 16 / sizeof(T);
+
+// One round of K stages on the position bits [b_lo, b_lo + K).  Stage i of
+// Algorithm 1 pairs bit b = n - i; its twiddle is zeta_i^(pos mod 2^b), which is
+// entry (1 << b) + (pos mod 2^b) of the per-stage ("heap") table, so that lanes
+// with consecutive positions read consecutive entries.
+// LowRound: b_lo = 0, the twiddle indices are compile-time constants and are
+// read from global memory with scalar loads; the butterflies with twiddle 1
+// skip the product.  Otherwise the twiddles come from the LDS copy `tws`.
+// Src/Dst provide load/store of one position, and of kVec consecutive
+// positions when their kContig flag is set.
+template <bool Lazy, int N_LOG, int K, bool LowRound, class Src, class Dst>
+__device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws, const Tw2 *__restrict__ twg, T p,
+                                       T p2, const Src &src, const Dst &dst) {
+  constexpr int groups = 1 << (N_LOG - K);
+  constexpr int M = 1 << K;
+#pragma unroll 1
+  for (int gi = t; gi < groups; gi += tpt) {
+    const int low = gi & ((1 << b_lo) - 1);
+    const int base = ((gi >> b_lo) << (b_lo + K)) | low;
+    T v[M];
+    if constexpr (LowRound && Src::kContig && M >= kVec) {
+#pragma unroll
+      for (int e = 0; e < M; e += kVec) src.load_vec(base + e, &v[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < M; ++e) v[e] = src.load(base | (e << b_lo));
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int hb = kInverse ? s : K - 1 - s;
+#pragma unroll
+      for (int e = 0; e < M; ++e) {
+        if (e & (1 << hb)) continue;
+        if constexpr (LowRound) {
+          const int kk = e & ((1 << hb) - 1);
+          if (kk == 0) {
+            bfly_w1<Lazy>(v[e], v[e | (1 << hb)], p, p2);
+          } else {
+            const Tw2 tw = twg[(1 << hb) + kk];
+            bfly<Lazy>(v[e], v[e | (1 << hb)], tw.w, tw.wp, p, p2);
+          }
+        } else {
+          const int b = b_lo + hb;
+          const int pos = base | (e << b_lo);
+          const Tw2 tw = tws[(1 << b) + (pos & ((1 << b) - 1))];
+          bfly<Lazy>(v[e], v[e | (1 << hb)], tw.w, tw.wp, p, p2);
+        }
+      }
+    }
+    if constexpr (LowRound && Dst::kContig && M >= kVec) {
+#pragma unroll
+      for (int e = 0; e < M; e += kVec) dst.store_vec(base + e, &v[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < M; ++e) dst.store(base | (e << b_lo), v[e]);
+    }
+  }
+}
+
+// Final reduction of a lazy result: forward outputs lie in [0,2p), inverse in [0,4p).
+template <bool Lazy>
+__device__ __forceinline__ T reduce_final(T x, T p) {
+  if constexpr (!Lazy) return x;
+  if constexpr (kInverse) x = csub<T>(x, p + p);
+  return csub<T>(x, p);
+}
+
+struct KernelArgs {
+  BatchPtrs ptrs;
+  int nbatch;
+  int log_other;  // rows: log2(#rows); cols: log2(#columns)
+  int group;      // G
+  int normalize;  // reduce the final output to [0,p)
+  int scale;      // whole inverse: multiply by L^-1 (scale_w, scale_wp)
+  uint64_t p;
+  uint64_t scale_w, scale_wp;
+  const void *tw;  // per-stage table of (W, W') pairs, entry (1 << b) + k = omega_N^(+-(k << (n-1-b)))
+  const void *tt;  // cols: interleaved split twiddles laid out like the data
+};
+
+// What happens to a word on its way in from HBM and out to HBM.
+template <bool Lazy, bool Cols>
+struct Edge {
+  T p;
+  int normalize, scale;
+  T sw, swp;
+  const Tw2 *__restrict__ tt;  // split twiddles of this thread's column (cols), stride C
+  size_t C;
+  __device__ __forceinline__ T in(T x, int pos) const {
+    if constexpr (Cols && kInverse) {  // conj(omega)^(col s) L^-1 before the column transform
+      const Tw2 f = tt[(size_t)pos * C];
+      x = shoup_lazy<Wd>(x, f.w, f.wp, p);
+      if constexpr (!Lazy) x = csub<T>(x, p);
+    }
+    return x;
+  }
+  __device__ __forceinline__ T out(T x, int pos) const {
+    if constexpr (Cols && !kInverse) {  // omega^(col s) after the column transform
+      const Tw2 f = tt[(size_t)pos * C];
+      x = shoup_lazy<Wd>(x, f.w, f.wp, p);
+      if constexpr (!Lazy) x = csub<T>(x, p);
+    } else if constexpr (!Cols && kInverse) {
+      if (scale) {  // whole inverse transform: times L^-1, then reduced
+        x = shoup_lazy<Wd>(x, sw, swp, p);
+        if (normalize) x = csub<T>(x, p);
+      } else if (normalize) {
+        x = reduce_final<Lazy>(x, p);
+      }
+    } else {
+      if (normalize) x = reduce_final<Lazy>(x, p);
+    }
+    return x;
+  }
+};
+
+// HBM side: position pos of this thread's sub-transform at gsub[pos * stride].
+template <bool Lazy, bool Cols>
+struct GlobalIO {
+  static constexpr bool kContig = !Cols;
+  T *gsub;
+  size_t stride;
+  Edge<Lazy, Cols> edge;
+  __device__ __forceinline__ T load(int pos) const { return edge.in(gsub[(size_t)pos * stride], pos); }
+  __device__ __forceinline__ void store(int pos, T x) const { gsub[(size_t)pos * stride] = edge.out(x, pos); }
+  // kContig only: kVec consecutive positions, pos a multiple of kVec
+  __device__ __forceinline__ void load_vec(int pos, T *v) const {
+    const uint4 q = *reinterpret_cast<const uint4 *>(gsub + pos);
+    const T *w = reinterpret_cast<const T *>(&q);
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) v[i] = edge.in(w[i], pos + i);
+  }
+  __device__ __forceinline__ void store_vec(int pos, const T *v) const {
+    uint4 q;
+    T *w = reinterpret_cast<T *>(&q);
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) w[i] = edge.out(v[i], pos + i);
+    *reinterpret_cast<uint4 *>(gsub + pos) = q;
+  }
+};
+
+// LDS side.  Columns: element (g, pos) at pad1(pos) * G + g, one pad word per 32
+// positions, so both rounds' access patterns hit distinct banks.  Rows: element
+// (g, pos) at g * pitch + pad4(pos), four pad words per 32 positions, which keeps
+// 16-byte alignment of each group of 4 for vector accesses of the low round.
+template <bool Cols>
+struct LdsIO {
+  static constexpr bool kContig = !Cols;
+  T *tile;
+  int G, g, pitch;
+  __device__ __forceinline__ int idx(int pos) const {
+    if constexpr (Cols) return (pos + (pos >> 5)) * G + g;
+    else return g * pitch + pos + ((pos >> 5) << 2);
+  }
+  __device__ __forceinline__ T load(int pos) const { return tile[idx(pos)]; }
+  __device__ __forceinline__ void store(int pos, T x) const { tile[idx(pos)] = x; }
+  __device__ __forceinline__ void load_vec(int pos, T *v) const {
+    const uint4 q = *reinterpret_cast<const uint4 *>(tile + idx(pos));
+    const T *w = reinterpret_cast<const T *>(&q);
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) v[i] = w[i];
+  }
+  __device__ __forceinline__ void store_vec(int pos, const T *v) const {
+    uint4 q;
+    T *w = reinterpret_cast<T *>(&q);
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) w[i] = v[i];
+    *reinterpret_cast<uint4 *>(tile + idx(pos)) = q;
+  }
+};
+
+// Padded LDS words per sub-transform (rows: row pitch; cols: rows of the tile).
+template <bool Cols>
+constexpr int padded_len(int N) {
+  return Cols ? N + N / 32 : N + (N >= 32 ? N / 8 : 0);
+}
+
+template <bool Lazy, bool Cols, int KH, int KM, int KL>
+__global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
+  constexpr int N_LOG = KH + KM + KL;
+  constexpr int N = 1 << N_LOG;
+  constexpr int KMAX = KH > KL ? (KH > KM ? KH : KM) : (KL > KM ? KL : KM);
+  constexpr int TPT = 1 << (N_LOG - KMAX);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const T p = (T)a.p, p2 = p + p;
+  const int G = a.group;
+  const Tw2 *__restrict__ twg = static_cast<const Tw2 *>(a.tw);
+
+  // block -> (transform b, unit): blocks are dealt to the 8 XCDs round-robin.  Each
+  // XCD takes a contiguous eighth of the units for every transform, units fastest:
+  // neighbouring column groups (which share 128-byte lines) then run together in one
+  // L2, and an XCD re-reads only its own eighth of the split twiddles.
+  const int units = (int)(gridDim.x / a.nbatch);
+  int b, unit;
+  if ((units & 7) == 0) {
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, per = units >> 3;
+    unit = x * per + j % per;
+    b = j / per;
+  } else {
+    unit = blockIdx.x % units;
+    b = blockIdx.x / units;
+  }
+
+  int g, t;
+  if constexpr (Cols) {
+    g = threadIdx.x % G;
+    t = threadIdx.x / G;
+  } else {
+    t = threadIdx.x % TPT;
+    g = threadIdx.x / TPT;
+  }
+  T *const gbase = reinterpret_cast<T *>(a.ptrs.ptr[b]);
+  const size_t C = (size_t)1 << a.log_other;
+  Edge<Lazy, Cols> edge{p, a.normalize, a.scale, (T)a.scale_w, (T)a.scale_wp, nullptr, C};
+  GlobalIO<Lazy, Cols> gio;
+  if constexpr (Cols) {
+    const size_t col = (size_t)unit * G + g;
+    gio.gsub = gbase + col;
+    gio.stride = C;
+    edge.tt = static_cast<const Tw2 *>(a.tt) + col;
+  } else {
+    gio.gsub = gbase + ((size_t)unit * G + g) * N;
+    gio.stride = 1;
+  }
+  gio.edge = edge;
+
+  static_assert(KH > 0 || KM == 0, "a single round has no middle round");
+  if constexpr (KH == 0) {
+    // one round, HBM to HBM
+    round_k<Lazy, N_LOG, KL, true>(0, t, TPT, nullptr, twg, p, p2, gio, gio);
+  } else {
+    Tw2 *tws = reinterpret_cast<Tw2 *>(smem_raw);
+    T *tile = reinterpret_cast<T *>(tws + N);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = twg[i];
+    const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
+    if constexpr (!kInverse) {
+      __syncthreads();  // twiddle table staged
+      round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, gio, lio);
+      __syncthreads();
+      if constexpr (KM > 0) {
+        round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
+        __syncthreads();
+      }
+      round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, gio);
+    } else {
+      round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, gio, lio);
+      __syncthreads();  // tile and twiddle table complete
+      if constexpr (KM > 0) {
+        round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
+        __syncthreads();
+      }
+      round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, lio, gio);
+    }
+  }
+}
+
+template <bool Lazy, bool Cols, int KH, int KM, int KL>
+hipError_t launch_k(const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t stream) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<Lazy, Cols, KH, KM, KL>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_pass<Lazy, Cols, KH, KM, KL>), dim3(blocks), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
+// Round splits per word size; must agree with pass_split().
+template <bool Lazy, bool Cols>
+hipError_t dispatch_n(int n, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t s) {
+#define HNTT_CASE(N, KH, KM, KL) \
+  case N: return launch_k<Lazy, Cols, KH, KM, KL>(a, blocks, threads, lds, s);
+  switch (n) {
+    HNTT_CASE(1, 0, 0, 1)
+    HNTT_CASE(2, 0, 0, 2)
+    HNTT_CASE(3, 0, 0, 3)
+    HNTT_CASE(4, 0, 0, 4)
+    HNTT_CASE(5, 0, 0, 5)
+#if HNTT_WORD == 32
+    HNTT_CASE(6, 0, 0, 6)
+#else
+    HNTT_CASE(6, 3, 0, 3)
+#endif
+    HNTT_CASE(7, 4, 0, 3)
+    HNTT_CASE(8, 4, 0, 4)
+#if HNTT_WORD == 32
+    HNTT_CASE(9, 5, 0, 4)
+    HNTT_CASE(10, 5, 0, 5)
+    HNTT_CASE(11, 6, 0, 5)
+#else
+    HNTT_CASE(9, 3, 3, 3)
+    HNTT_CASE(10, 4, 3, 3)
+    HNTT_CASE(11, 4, 4, 3)
+#endif
+    HNTT_CASE(12, 4, 4, 4)
+    default: return hipErrorInvalidValue;
+  }
+#undef HNTT_CASE
+}
+
+}  // namespace HNTT_NS
+
+#if HNTT_WORD == 32 && HNTT_INVERSE == 0
+#define HNTT_LAUNCH_NAME launch_pass_u32_fwd
+#elif HNTT_WORD == 32
+#define HNTT_LAUNCH_NAME launch_pass_u32_inv
+#elif HNTT_INVERSE == 0
+#define HNTT_LAUNCH_NAME launch_pass_u64_fwd
+#else
+#define HNTT_LAUNCH_NAME launch_pass_u64_inv
+#endif
+
+hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream) {
+  const int n = pp.n;
+  if (n < 1 || n > kMaxPassLog) return hipErrorInvalidValue;
+  const bool cols = pp.kind == PassKind::kCols;
+  const int log_other = pp.kind == PassKind::kWhole ? 0 : pp.log_other;
+  const int units = (1 << log_other) / pp.group;
+  if (units < 1 || pp.nbatch < 1 || pp.nbatch > kMaxBatchPerLaunch) return hipErrorInvalidValue;
+  const int threads = pass_tpt(n, HNTT_WORD) * pp.group;
+  const size_t lds = pass_lds_bytes(pp);
+  if (threads > kMaxPassThreads || (lds == 0 && pass_split(n, HNTT_WORD).kh > 0)) return hipErrorInvalidValue;
+  HNTT_NS::KernelArgs a{};
+  a.ptrs = ptrs;
+  a.nbatch = pp.nbatch;
+  a.log_other = log_other;
+  a.group = pp.group;
+  a.normalize = pp.normalize ? 1 : 0;
+  a.scale = (pp.kind == PassKind::kWhole && pp.inverse) ? 1 : 0;
+  a.p = pp.p;
+  a.scale_w = pp.scale_w;
+  a.scale_wp = pp.scale_wp;
+  a.tw = pp.tw;
+  a.tt = pp.tt;
+  const int blocks = units * pp.nbatch;
+  using namespace HNTT_NS;
+  if (pp.lazy) return cols ? dispatch_n<true, true>(n, a, blocks, threads, lds, stream)
+                           : dispatch_n<true, false>(n, a, blocks, threads, lds, stream);
+  return cols ? dispatch_n<false, true>(n, a, blocks, threads, lds, stream)
+              : dispatch_n<false, false>(n, a, blocks, threads, lds, stream);
+}
+
+}  // namespace hntt

@@ -68,6 +68,9 @@ SIGNATURES = {
     "hntt_find_prime": (_c_u64, [_c_u32, _c_u32]),
     "hntt_shoup_constant": (ctypes.c_int, [_c_u64, _c_u64, _c_u32, ctypes.POINTER(_c_u64)]),
     "hntt_validate": (ctypes.c_int, [_c_vp, ctypes.POINTER(Desc), ctypes.c_size_t, _c_u32]),
+    "hntt_trace_enable": (ctypes.c_int, [_c_vp, ctypes.c_int]),
+    "hntt_trace_read": (ctypes.c_int, [_c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "hntt_trace_reset": (ctypes.c_int, [_c_vp]),
     "hntt_debug_butterfly": (ctypes.c_int, [_c_vp, ctypes.c_int, _c_u32, _c_u64, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                             _c_vp, ctypes.c_size_t, _c_vp]),
 }
@@ -228,6 +231,23 @@ class Context:
         self._check(self.lib.hntt_polymul_crt(self.handle, arr, len(pairs), PLAIN if plain else 0,
                                               _stream_handle(stream, dev)))
         return outs
+
+    # -- kernel timing -----------------------------------------------------------------------------
+    def trace(self, enable: bool = True):
+        self._check(self.lib.hntt_trace_enable(self.handle, int(enable)))
+
+    def trace_reset(self):
+        self._check(self.lib.hntt_trace_reset(self.handle))
+
+    def trace_read(self) -> dict:
+        """Per-kernel launch counts and total milliseconds since the last reset."""
+        import json
+        n = ctypes.c_size_t(0)
+        self.lib.hntt_trace_read(self.handle, None, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value + 64)
+        n2 = ctypes.c_size_t(len(buf))
+        self._check(self.lib.hntt_trace_read(self.handle, buf, ctypes.byref(n2)))
+        return json.loads(buf.value.decode())
 
     def debug_butterfly(self, kind: int, p: int, x, y, w, wp, xo, yo, stream=None):
         wb = _word_bits(x)

@@ -95,6 +95,8 @@ def _desc(p=P30, omega=258648936, data=4096, l=10, wb=32):
 @pytest.mark.parametrize("kw,status,msg", [
     (dict(data=0), hntt.EINVAL, "NULL"),
     (dict(data=4098), hntt.EINVAL, "aligned"),
+    (dict(data=4100), hntt.EINVAL, "aligned to 16"),
+    (dict(data=4104, l=1, omega=P30 - 1), hntt.OK, ""),
     (dict(wb=16), hntt.EINVAL, "word_bits"),
     (dict(l=0), hntt.EINVAL, "log2_len"),
     (dict(l=31), hntt.EINVAL, "log2_len"),
