@@ -44,6 +44,7 @@ def parse():
                     help="transforms (forward + inverse, length 2^20) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in schedule instead of the autotuner's")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for HBM byte counters)")
     return ap.parse_args()
@@ -147,7 +148,14 @@ def main():
 
     bfly_step = 2 * cfg.butterflies
     res = {}
+    schedules = {}
+    from paper_1205_2926_amd import autotune
     for policy in (["lazy"] if args.no_plain else ["lazy", "plain"]):
+        if args.no_tune:
+            ctx.set_tuning(l, cfg.word_bits)
+        else:  # each butterfly gets its own best schedule (cached per GPU and shape)
+            autotune.tune(ctx, x, p, w, plain=policy == "plain")
+        schedules[policy] = ctx.get_plan(l, cfg.word_bits)
         sec, kernels = time_steps(ctx, x, p, w, policy == "plain", args.steps, args.warmup)
         res[policy] = (sec, kernels)
     assert np.array_equal(x.cpu().numpy().view(np.uint32), x_np), "data changed across steps"
@@ -186,10 +194,11 @@ def main():
         "roofline": roof,
         "hbm_frac_compulsory": (2 * bytes_alg) / sec / 1e9 / HBM_PEAK_GBS,
         "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in kernels.items()},
+        "schedule": schedules.get("lazy"),
     }
     if "plain" in res:
         psec, pk = res["plain"]
-        out["plain"] = {"value": bfly_step / psec, "ms_per_step": psec * 1e3,
+        out["plain"] = {"value": bfly_step / psec, "ms_per_step": psec * 1e3, "schedule": schedules["plain"],
                         "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in pk.items()}}
         out["lazy_over_plain"] = psec / sec
     if not args.no_cpu_baseline:

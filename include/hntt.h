@@ -172,6 +172,29 @@ int hntt_shoup_constant(uint64_t w, uint64_t p, uint32_t word_bits, uint64_t *wp
 int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags);
 
 /* ---------------------------------------------------------------------------
+ * Schedule tuning.  A transform of length 2^l above the one-workgroup limit
+ * runs as a column pass and a row pass; g_cols / g_rows are the sub-transforms
+ * (columns / rows) one workgroup owns in each, and batch_chunk the number of
+ * transforms that go through all passes before the next chunk starts (so a
+ * chunk's intermediate result can stay in the last-level cache).  Fields set
+ * to 0 keep the built-in choice.  hntt_set_tuning overrides the schedule for
+ * (log2_len, word_bits) on this context (EINVAL if a value does not fit the
+ * kernels: powers of two, thread and LDS limits, batch_chunk <= 64);
+ * hntt_get_plan reports the schedule in effect.  Results never depend on the
+ * schedule; only speed does.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t log2_len;
+  uint32_t word_bits;
+  uint32_t g_cols;
+  uint32_t g_rows;
+  uint32_t batch_chunk;
+  uint32_t reserved; /* must be 0 */
+} hntt_tuning;
+int hntt_set_tuning(hntt_ctx *ctx, const hntt_tuning *t);
+int hntt_get_plan(hntt_ctx *ctx, uint32_t log2_len, uint32_t word_bits, hntt_tuning *out);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (tracing).  While enabled, every kernel the context launches
  * is bracketed by two HIP events recorded on its launch stream.
  * hntt_trace_read waits for the pending events and writes, as JSON text,

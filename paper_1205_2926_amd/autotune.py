@@ -1,0 +1,132 @@
+"""Schedule autotuner for the transform passes.
+
+For a (length, word size, batch) shape it times forward+inverse transforms on
+the GPU under every legal schedule in a small search space (columns per
+workgroup in the column pass, rows per workgroup in the row pass, transforms
+per chunk) and installs the fastest one on the context with
+``Context.set_tuning``.  Results are cached in a JSON file keyed by GPU name
+and shape (``$HNTT_TUNE_CACHE``, default ``~/.cache/hntt/tune.json``).  The
+schedule never changes results, only speed.
+
+CLI: ``python -m paper_1205_2926_amd.autotune --log2-len 20 --batch 64``
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import time
+
+import torch
+
+from . import hntt
+
+CACHE = os.environ.get("HNTT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hntt", "tune.json"))
+SPACE = {"g_cols": [4, 8, 16], "g_rows": [1, 2, 4, 8, 16], "batch_chunk": [8, 16, 32, 64]}
+
+
+def _key(log2_len, word_bits, batch, plain):
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return f"{name}|l={log2_len}|w={word_bits}|b={batch}|{'plain' if plain else 'lazy'}"
+
+
+def load_cache(path: str = CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: dict, path: str = CACHE):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time(ctx, x, p, w, plain, reps):
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.ntt_forward(x, p, w, plain=plain)
+    ctx.ntt_inverse(x, p, w, plain=plain)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        ctx.ntt_forward(x, p, w, plain=plain)
+        ctx.ntt_inverse(x, p, w, plain=plain)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def candidates(ctx, log2_len, word_bits, batch):
+    """Legal schedules of the search space (the library rejects the others)."""
+    out = []
+    for gc, gr, ch in itertools.product(SPACE["g_cols"], SPACE["g_rows"], SPACE["batch_chunk"]):
+        if ch > max(batch, 8) * 2:
+            continue
+        try:
+            ctx.set_tuning(log2_len, word_bits, gc, gr, ch)
+        except hntt.HnttError:
+            continue
+        out.append({"g_cols": gc, "g_rows": gr, "batch_chunk": ch})
+    ctx.set_tuning(log2_len, word_bits, 0, 0, 0)
+    return out
+
+
+def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: int = 3, use_cache: bool = True,
+         verbose: bool = False) -> dict:
+    """Pick and install the fastest schedule for transforms shaped like x ([batch, 2^l])."""
+    batch, L = x.shape
+    log2_len = L.bit_length() - 1
+    word_bits = x.element_size() * 8
+    key = _key(log2_len, word_bits, batch, plain)
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        best = cache[key]["best"]
+        ctx.set_tuning(log2_len, word_bits, best["g_cols"], best["g_rows"], best["batch_chunk"])
+        return cache[key]
+    ctx.set_tuning(log2_len, word_bits, 0, 0, 0)
+    default = dict(ctx.get_plan(log2_len, word_bits))
+    trials = []
+    t0 = time.time()
+    for cand in candidates(ctx, log2_len, word_bits, batch):
+        ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
+        ms = _time(ctx, x, p, omega, plain, reps)
+        trials.append({**cand, "ms": ms})
+        if verbose:
+            print(f"  {cand} -> {ms:.4f} ms", flush=True)
+    best = min(trials, key=lambda r: r["ms"]) if trials else {**default, "ms": None}
+    ctx.set_tuning(log2_len, word_bits, best["g_cols"], best["g_rows"], best["batch_chunk"])
+    rec = {"best": best, "default": default, "trials": len(trials), "tune_s": time.time() - t0}
+    if use_cache:
+        cache[key] = rec
+        save_cache(cache)
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--log2-len", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--word-bits", type=int, default=32)
+    ap.add_argument("--plain", action="store_true")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--no-cache", action="store_true")
+    args = ap.parse_args()
+    from .workloads import P30, P62, uniform_residues
+    import numpy as np
+    p = P30 if args.word_bits == 32 else P62
+    w = hntt.root_of_unity(p, args.log2_len)
+    dt = np.uint32 if args.word_bits == 32 else np.uint64
+    host = uniform_residues(99, (args.batch, 1 << args.log2_len), p, dt)
+    x = torch.from_numpy(host.view(np.int32 if args.word_bits == 32 else np.int64)).cuda()
+    ctx = hntt.Context(0)
+    rec = tune(ctx, x, p, w, plain=args.plain, reps=args.reps, use_cache=not args.no_cache, verbose=True)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

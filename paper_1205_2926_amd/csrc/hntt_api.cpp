@@ -142,10 +142,55 @@ Plan make_plan(int l, int word_bits) {
   int g = word_bits == 32 ? 16 : 8;
   while (g > 1 && (pass_tpt(pl.r, word_bits) * g > kMaxPassThreads || g > (1 << pl.c) || !lds_ok(pl.r, g))) g >>= 1;
   pl.g_cols = g;
-  // row pass: about 256 threads per workgroup
-  int gr = std::max(1, 256 / pass_tpt(pl.c, word_bits));
+  // row pass: up to 512 threads per workgroup (the fastest row-pass shape measured at L = 2^20)
+  int gr = std::max(1, kMaxPassThreads / pass_tpt(pl.c, word_bits));
   while (gr > 1 && (gr > (1 << pl.r) || !lds_ok(pl.c, gr))) gr >>= 1;
   pl.g_rows = gr;
+  pl.chunk = kMaxBatchPerLaunch;
+  return pl;
+}
+
+// A schedule override is legal when every pass fits the kernels' limits.
+int check_tuning(const hntt_tuning &t, std::string *why) {
+  auto fail = [&](const char *m) {
+    if (why) *why = m;
+    return HNTT_EINVAL;
+  };
+  if (t.word_bits != 32 && t.word_bits != 64) return fail("word_bits must be 32 or 64");
+  const int lmax = max_whole_log((int)t.word_bits);
+  if (t.log2_len < 1 || (int)t.log2_len > 2 * lmax) return fail("log2_len outside the two-pass range");
+  if (t.reserved) return fail("reserved must be 0");
+  if (t.batch_chunk > (uint32_t)kMaxBatchPerLaunch) return fail("batch_chunk above the per-launch limit");
+  const Plan base = make_plan((int)t.log2_len, (int)t.word_bits);
+  auto pow2 = [](uint32_t v) { return v && !(v & (v - 1)); };
+  auto fits = [&](PassKind kind, int n, uint32_t g) {
+    PassParams pp{};
+    pp.kind = kind;
+    pp.word_bits = (int)t.word_bits;
+    pp.n = n;
+    pp.group = (int)g;
+    const bool lds_ok = pass_split(n, (int)t.word_bits).kh == 0 || pass_lds_bytes(pp) != 0;
+    return lds_ok && pass_tpt(n, (int)t.word_bits) * (int)g <= kMaxPassThreads;
+  };
+  if (t.g_cols) {
+    if (!base.split || !pow2(t.g_cols) || t.g_cols > (1u << base.c) || !fits(PassKind::kCols, base.r, t.g_cols))
+      return fail("g_cols must be a power of two that fits the column pass");
+  }
+  if (t.g_rows) {
+    if (!base.split || !pow2(t.g_rows) || t.g_rows > (1u << base.r) || !fits(PassKind::kRows, base.c, t.g_rows))
+      return fail("g_rows must be a power of two that fits the row pass");
+  }
+  return HNTT_OK;
+}
+
+Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits) {
+  Plan pl = make_plan(l, word_bits);
+  auto it = ctx->tuning.find(std::make_pair(l, word_bits));
+  if (it != ctx->tuning.end()) {
+    if (it->second.g_cols) pl.g_cols = (int)it->second.g_cols;
+    if (it->second.g_rows) pl.g_rows = (int)it->second.g_rows;
+    if (it->second.batch_chunk) pl.chunk = (int)it->second.batch_chunk;
+  }
   return pl;
 }
 
@@ -288,13 +333,14 @@ hipError_t launch_traced(hntt_ctx *ctx, const PassParams &pp, const BatchPtrs &b
 }
 
 // Run every pass of one transform direction over a batch sharing (p, omega, l, word_bits).
-int run_transform(hntt_ctx *ctx, const Tables &t, const std::vector<void *> &ptrs, uint64_t p, int l, int bits,
-                  bool inverse, uint32_t flags, hipStream_t stream) {
+int run_transform(hntt_ctx *ctx, const Tables &t, const Plan &plan, const std::vector<void *> &ptrs, uint64_t p,
+                  int l, int bits, bool inverse, uint32_t flags, hipStream_t stream) {
   const bool lazy = !(flags & HNTT_PLAIN);
   const bool norm = !(flags & HNTT_NO_NORMALIZE);
-  for (size_t off = 0; off < ptrs.size(); off += kMaxBatchPerLaunch) {
+  const size_t chunk = (size_t)std::max(1, std::min(plan.chunk, kMaxBatchPerLaunch));
+  for (size_t off = 0; off < ptrs.size(); off += chunk) {
     BatchPtrs bp{};
-    const int nb = (int)std::min<size_t>(kMaxBatchPerLaunch, ptrs.size() - off);
+    const int nb = (int)std::min<size_t>(chunk, ptrs.size() - off);
     for (int i = 0; i < nb; ++i) bp.ptr[i] = reinterpret_cast<uint64_t>(ptrs[off + i]);
     PassParams pp{};
     pp.word_bits = bits;
@@ -303,7 +349,7 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const std::vector<void *> &ptr
     pp.nbatch = nb;
     pp.p = p;
     hipError_t e;
-    if (!t.plan.split) {
+    if (!plan.split) {
       pp.kind = PassKind::kWhole;
       pp.n = l;
       pp.log_other = 0;
@@ -317,15 +363,15 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const std::vector<void *> &ptr
     }
     PassParams cols = pp, rows = pp;
     cols.kind = PassKind::kCols;
-    cols.n = t.plan.r;
-    cols.log_other = t.plan.c;
-    cols.group = t.plan.g_cols;
+    cols.n = plan.r;
+    cols.log_other = plan.c;
+    cols.group = plan.g_cols;
     cols.tw = inverse ? t.inv : t.fwd;
     cols.tt = inverse ? t.tt_inv : t.tt_fwd;
     rows.kind = PassKind::kRows;
-    rows.n = t.plan.c;
-    rows.log_other = t.plan.r;
-    rows.group = t.plan.g_rows;
+    rows.n = plan.c;
+    rows.log_other = plan.r;
+    rows.group = plan.g_rows;
     rows.tw = inverse ? t.row_inv : t.row_fwd;
     if (!inverse) {
       cols.normalize = false;
@@ -365,7 +411,8 @@ int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, v
     const int l = std::get<2>(kv.first), bits = std::get<3>(kv.first);
     const Tables *t = nullptr;
     if ((rc = get_tables(ctx, p, omega, l, bits, &t))) return rc;
-    if ((rc = run_transform(ctx, *t, kv.second, p, l, bits, inverse, flags, (hipStream_t)stream))) return rc;
+    const Plan plan = effective_plan(ctx, l, bits);
+    if ((rc = run_transform(ctx, *t, plan, kv.second, p, l, bits, inverse, flags, (hipStream_t)stream))) return rc;
   }
   return HNTT_OK;
 }
@@ -452,6 +499,29 @@ int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint3
     hipError_t e = launch_pointwise((int)d.word_bits, d.p, d.a, d.b, d.c, d.len, (hipStream_t)stream);
     if (e != hipSuccess) return hip_status(ctx, e, "launch(pointwise)");
   }
+  return HNTT_OK;
+}
+
+int hntt_set_tuning(hntt_ctx *ctx, const hntt_tuning *t) {
+  if (!ctx || !t) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  std::string why;
+  if (check_tuning(*t, &why)) return set_error(ctx, HNTT_EINVAL, "%s", why.c_str());
+  ctx->tuning[std::make_pair((int)t->log2_len, (int)t->word_bits)] = *t;
+  return HNTT_OK;
+}
+
+int hntt_get_plan(hntt_ctx *ctx, uint32_t log2_len, uint32_t word_bits, hntt_tuning *out) {
+  if (!ctx || !out || (word_bits != 32 && word_bits != 64)) return HNTT_EINVAL;
+  const int lmax = max_whole_log((int)word_bits);
+  if (log2_len < 1 || (int)log2_len > 2 * lmax) return set_error(ctx, HNTT_EUNSUPPORTED, "no plan for this length");
+  const Plan pl = effective_plan(ctx, (int)log2_len, (int)word_bits);
+  out->log2_len = log2_len;
+  out->word_bits = word_bits;
+  out->g_cols = pl.split ? (uint32_t)pl.g_cols : 0;
+  out->g_rows = pl.split ? (uint32_t)pl.g_rows : 0;
+  out->batch_chunk = (uint32_t)pl.chunk;
+  out->reserved = 0;
   return HNTT_OK;
 }
 

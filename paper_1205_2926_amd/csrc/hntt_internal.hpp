@@ -30,6 +30,7 @@ struct Plan {
   int c;       // log2 of the row length (split)
   int g_cols;  // columns per workgroup in the column pass
   int g_rows;  // rows per workgroup in the row pass
+  int chunk;   // transforms per launch; every pass runs on one chunk before the next chunk
 };
 
 // Device twiddle tables for one (p, omega, l, word_bits), each an array of
@@ -63,6 +64,7 @@ struct hntt_ctx {
   std::string last_error;
   std::map<uint64_t, bool> prime_cache;
   std::map<std::tuple<uint64_t, uint64_t, int, int>, hntt::Tables> tables;
+  std::map<std::pair<int, int>, hntt_tuning> tuning;  // (log2_len, word_bits) -> schedule override
   std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
   bool trace = false;
   std::vector<hntt::TraceEvent> trace_pending;
@@ -80,6 +82,8 @@ struct hntt_ctx {
 namespace hntt {
 int check_desc(hntt_ctx *ctx, const hntt_desc &d, uint32_t flags);
 Plan make_plan(int l, int word_bits);
+Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits);
+int check_tuning(const hntt_tuning &t, std::string *why);
 int ensure_device(hntt_ctx *ctx);
 int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const Tables **out);
 // Launch wrapper that records HIP events around the launch when tracing is on.

@@ -52,9 +52,14 @@ using Wd = Word64;
 using T = typename Wd::T;
 constexpr bool kInverse = HNTT_INVERSE != 0;
 
-struct alignas(2 * sizeof(T)) Tw2 {
-  T w, wp;
-};
+// Global (HBM) address space: lets the compiler emit global_* instead of flat_*
+// memory instructions, which would also count against the LDS wait counter.
+#define HNTT_GLOBAL __attribute__((address_space(1)))
+
+// A twiddle W and its Shoup constant W' as one 2-word vector (.x = W, .y = W').
+typedef T Tw2 __attribute__((ext_vector_type(2)));
+// 16 bytes moved by one vector memory instruction.
+typedef uint32_t Vec16 __attribute__((ext_vector_type(4)));
 
 template <bool Lazy>
 __device__ __forceinline__ void bfly(T &x, T &y, T w, T wp, T p, T p2) {
@@ -91,7 +96,7 @@ constexpr int kVec = 16 / sizeof(T);
 // Src/Dst provide load/store of one position, and of kVec consecutive
 // positions when their kContig flag is set.
 template <bool Lazy, int N_LOG, int K, bool LowRound, class Src, class Dst>
-__device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws, const Tw2 *__restrict__ twg, T p,
+__device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws, const HNTT_GLOBAL Tw2 *__restrict__ twg, T p,
                                        T p2, const Src &src, const Dst &dst) {
   constexpr int groups = 1 << (N_LOG - K);
   constexpr int M = 1 << K;
@@ -119,13 +124,13 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws
             bfly_w1<Lazy>(v[e], v[e | (1 << hb)], p, p2);
           } else {
             const Tw2 tw = twg[(1 << hb) + kk];
-            bfly<Lazy>(v[e], v[e | (1 << hb)], tw.w, tw.wp, p, p2);
+            bfly<Lazy>(v[e], v[e | (1 << hb)], tw.x, tw.y, p, p2);
           }
         } else {
           const int b = b_lo + hb;
           const int pos = base | (e << b_lo);
           const Tw2 tw = tws[(1 << b) + (pos & ((1 << b) - 1))];
-          bfly<Lazy>(v[e], v[e | (1 << hb)], tw.w, tw.wp, p, p2);
+          bfly<Lazy>(v[e], v[e | (1 << hb)], tw.x, tw.y, p, p2);
         }
       }
     }
@@ -166,12 +171,12 @@ struct Edge {
   T p;
   int normalize, scale;
   T sw, swp;
-  const Tw2 *__restrict__ tt;  // split twiddles of this thread's column (cols), stride C
+  const HNTT_GLOBAL Tw2 *__restrict__ tt;  // split twiddles of this thread's column (cols), stride C
   size_t C;
   __device__ __forceinline__ T in(T x, int pos) const {
     if constexpr (Cols && kInverse) {  // conj(omega)^(col s) L^-1 before the column transform
       const Tw2 f = tt[(size_t)pos * C];
-      x = shoup_lazy<Wd>(x, f.w, f.wp, p);
+      x = shoup_lazy<Wd>(x, f.x, f.y, p);
       if constexpr (!Lazy) x = csub<T>(x, p);
     }
     return x;
@@ -179,7 +184,7 @@ struct Edge {
   __device__ __forceinline__ T out(T x, int pos) const {
     if constexpr (Cols && !kInverse) {  // omega^(col s) after the column transform
       const Tw2 f = tt[(size_t)pos * C];
-      x = shoup_lazy<Wd>(x, f.w, f.wp, p);
+      x = shoup_lazy<Wd>(x, f.x, f.y, p);
       if constexpr (!Lazy) x = csub<T>(x, p);
     } else if constexpr (!Cols && kInverse) {
       if (scale) {  // whole inverse transform: times L^-1, then reduced
@@ -199,24 +204,24 @@ struct Edge {
 template <bool Lazy, bool Cols>
 struct GlobalIO {
   static constexpr bool kContig = !Cols;
-  T *gsub;
+  HNTT_GLOBAL T *gsub;
   size_t stride;
   Edge<Lazy, Cols> edge;
   __device__ __forceinline__ T load(int pos) const { return edge.in(gsub[(size_t)pos * stride], pos); }
   __device__ __forceinline__ void store(int pos, T x) const { gsub[(size_t)pos * stride] = edge.out(x, pos); }
   // kContig only: kVec consecutive positions, pos a multiple of kVec
   __device__ __forceinline__ void load_vec(int pos, T *v) const {
-    const uint4 q = *reinterpret_cast<const uint4 *>(gsub + pos);
+    const Vec16 q = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(gsub + pos);
     const T *w = reinterpret_cast<const T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) v[i] = edge.in(w[i], pos + i);
   }
   __device__ __forceinline__ void store_vec(int pos, const T *v) const {
-    uint4 q;
+    Vec16 q;
     T *w = reinterpret_cast<T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) w[i] = edge.out(v[i], pos + i);
-    *reinterpret_cast<uint4 *>(gsub + pos) = q;
+    *reinterpret_cast<HNTT_GLOBAL Vec16 *>(gsub + pos) = q;
   }
 };
 
@@ -236,17 +241,17 @@ struct LdsIO {
   __device__ __forceinline__ T load(int pos) const { return tile[idx(pos)]; }
   __device__ __forceinline__ void store(int pos, T x) const { tile[idx(pos)] = x; }
   __device__ __forceinline__ void load_vec(int pos, T *v) const {
-    const uint4 q = *reinterpret_cast<const uint4 *>(tile + idx(pos));
+    const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + idx(pos));
     const T *w = reinterpret_cast<const T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) v[i] = w[i];
   }
   __device__ __forceinline__ void store_vec(int pos, const T *v) const {
-    uint4 q;
+    Vec16 q;
     T *w = reinterpret_cast<T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) w[i] = v[i];
-    *reinterpret_cast<uint4 *>(tile + idx(pos)) = q;
+    *reinterpret_cast<Vec16 *>(tile + idx(pos)) = q;
   }
 };
 
@@ -265,7 +270,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const T p = (T)a.p, p2 = p + p;
   const int G = a.group;
-  const Tw2 *__restrict__ twg = static_cast<const Tw2 *>(a.tw);
+  const HNTT_GLOBAL Tw2 *__restrict__ twg = (const HNTT_GLOBAL Tw2 *)(a.tw);
 
   // block -> (transform b, unit): blocks are dealt to the 8 XCDs round-robin.  Each
   // XCD takes a contiguous eighth of the units for every transform, units fastest:
@@ -290,7 +295,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     t = threadIdx.x % TPT;
     g = threadIdx.x / TPT;
   }
-  T *const gbase = reinterpret_cast<T *>(a.ptrs.ptr[b]);
+  HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(a.ptrs.ptr[b]);
   const size_t C = (size_t)1 << a.log_other;
   Edge<Lazy, Cols> edge{p, a.normalize, a.scale, (T)a.scale_w, (T)a.scale_wp, nullptr, C};
   GlobalIO<Lazy, Cols> gio;
@@ -298,7 +303,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     const size_t col = (size_t)unit * G + g;
     gio.gsub = gbase + col;
     gio.stride = C;
-    edge.tt = static_cast<const Tw2 *>(a.tt) + col;
+    edge.tt = (const HNTT_GLOBAL Tw2 *)(a.tt) + col;
   } else {
     gio.gsub = gbase + ((size_t)unit * G + g) * N;
     gio.stride = 1;

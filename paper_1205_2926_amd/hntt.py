@@ -48,6 +48,11 @@ class PwDesc(ctypes.Structure):
                 ("reserved", _c_u32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("log2_len", _c_u32), ("word_bits", _c_u32), ("g_cols", _c_u32), ("g_rows", _c_u32),
+                ("batch_chunk", _c_u32), ("reserved", _c_u32)]
+
+
 class PolyDesc(ctypes.Structure):
     _fields_ = [("a", _c_vp), ("b", _c_vp), ("out", _c_vp), ("na", _c_u32), ("nb", _c_u32)]
 
@@ -68,6 +73,8 @@ SIGNATURES = {
     "hntt_find_prime": (_c_u64, [_c_u32, _c_u32]),
     "hntt_shoup_constant": (ctypes.c_int, [_c_u64, _c_u64, _c_u32, ctypes.POINTER(_c_u64)]),
     "hntt_validate": (ctypes.c_int, [_c_vp, ctypes.POINTER(Desc), ctypes.c_size_t, _c_u32]),
+    "hntt_set_tuning": (ctypes.c_int, [_c_vp, ctypes.POINTER(Tuning)]),
+    "hntt_get_plan": (ctypes.c_int, [_c_vp, _c_u32, _c_u32, ctypes.POINTER(Tuning)]),
     "hntt_trace_enable": (ctypes.c_int, [_c_vp, ctypes.c_int]),
     "hntt_trace_read": (ctypes.c_int, [_c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]),
     "hntt_trace_reset": (ctypes.c_int, [_c_vp]),
@@ -231,6 +238,16 @@ class Context:
         self._check(self.lib.hntt_polymul_crt(self.handle, arr, len(pairs), PLAIN if plain else 0,
                                               _stream_handle(stream, dev)))
         return outs
+
+    # -- schedule tuning ---------------------------------------------------------------------------
+    def set_tuning(self, log2_len: int, word_bits: int, g_cols: int = 0, g_rows: int = 0, batch_chunk: int = 0):
+        t = Tuning(log2_len, word_bits, g_cols, g_rows, batch_chunk, 0)
+        self._check(self.lib.hntt_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_plan(self, log2_len: int, word_bits: int) -> dict:
+        t = Tuning()
+        self._check(self.lib.hntt_get_plan(self.handle, log2_len, word_bits, ctypes.byref(t)))
+        return {k: getattr(t, k) for k in ("g_cols", "g_rows", "batch_chunk")}
 
     # -- kernel timing -----------------------------------------------------------------------------
     def trace(self, enable: bool = True):

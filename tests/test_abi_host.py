@@ -140,3 +140,19 @@ def test_transform_argument_errors_enqueue_nothing(ctx):
     assert rc == hntt.EINVAL and "flag" in ctx.last_error()
     assert ctx.lib.hntt_ntt_forward(ctx.handle, None, 0, 0, None) == hntt.OK
     assert ctx.lib.hntt_ntt_forward(None, None, 0, 0, None) == hntt.EINVAL
+
+
+def test_tuning_overrides_checked_on_host(ctx):
+    base = ctx.get_plan(20, 32)
+    assert base["g_cols"] >= 1 and base["g_rows"] >= 1 and base["batch_chunk"] == 64
+    ctx.set_tuning(20, 32, g_cols=8, g_rows=2, batch_chunk=16)
+    assert ctx.get_plan(20, 32) == {"g_cols": 8, "g_rows": 2, "batch_chunk": 16}
+    for bad in (dict(g_cols=3), dict(g_cols=64), dict(g_rows=1024), dict(batch_chunk=65)):
+        with pytest.raises(hntt.HnttError):
+            ctx.set_tuning(20, 32, **bad)
+    with pytest.raises(hntt.HnttError):
+        ctx.set_tuning(25, 32, g_cols=4)  # beyond the two-pass range
+    with pytest.raises(hntt.HnttError):
+        ctx.set_tuning(10, 32, g_cols=4)  # one-pass length has no column pass
+    ctx.set_tuning(20, 32)
+    assert ctx.get_plan(20, 32) == base

@@ -275,3 +275,30 @@ def test_pointwise_mul(ctx, orc, wb, p):
     np.testing.assert_array_equal(host(tc, dt).astype(np.uint64), orc.pointwise(a, b, p))
     ctx.pointwise_mul(ta, tb, ta, p)  # in place
     np.testing.assert_array_equal(host(ta, dt).astype(np.uint64), orc.pointwise(a, b, p))
+
+
+@pytest.mark.parametrize("wb,l", [(32, 20), (32, 13), (64, 22), (64, 15)])
+def test_schedule_independence(ctx, orc, wb, l):
+    """Every legal schedule gives bit-identical results (a cross-schedule check that would
+    expose LDS races or indexing mistakes tied to one tile shape)."""
+    from paper_1205_2926_amd.autotune import candidates
+    p, g = (P30, G30) if wb == 32 else (P62, G62)
+    w = _omega(orc, p, g, l)
+    dt = _np_dtype(wb)
+    batch = 12
+    x = uniform_residues(400 + l, (batch, 1 << l), p, dt)
+    ref = None
+    cands = candidates(ctx, l, wb, batch)
+    assert len(cands) >= 4
+    for cand in cands[:: max(1, len(cands) // 10)]:
+        ctx.set_tuning(l, wb, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
+        t = dev(x)
+        ctx.ntt_forward(t, p, w)
+        got = host(t, dt)
+        if ref is None:
+            ref = got
+            np.testing.assert_array_equal(got[0].astype(np.uint64), orc.forward(x[0], l, p, w))
+        np.testing.assert_array_equal(got, ref, err_msg=str(cand))
+        ctx.ntt_inverse(t, p, w)
+        np.testing.assert_array_equal(host(t, dt), x, err_msg=str(cand))
+    ctx.set_tuning(l, wb)
