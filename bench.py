@@ -91,6 +91,25 @@ def time_steps(ctx, x, p, w, plain, steps, warmup):
     return (t1 - t0) / steps, kernels
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_64x2^20_u32.json")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte counters, or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"].get(kernel)
+
+
 def cpu_baseline(cfg, w, x_np, sample):
     import numpy as np
     import oracle
@@ -173,7 +192,8 @@ def main():
     for r in (hbm, alu):
         r["frac"] = r["achieved"] / r["peak"]
     roof = dict(max((hbm, alu), key=lambda r: r["frac"]))
-    roof.update({"kernel": dom, "avg_launch_ms": avg_s * 1e3, "traffic": None,
+    roof.update({"kernel": dom, "avg_launch_ms": avg_s * 1e3, "traffic": measured_traffic(dom),
+                 "algorithmic_bytes": bytes_alg, "algorithmic_ops": ops_alg,
                  "other": (alu if roof["bound"] == "hbm" else hbm)})
 
     out = {
