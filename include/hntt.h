@@ -124,17 +124,25 @@ typedef struct {
 } hntt_pw_desc;
 int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint32_t flags, void *stream);
 
-/* Exact integer polynomial products (the application of Section 1) through
- * three NTT primes, 998244353, 754974721 and 167772161, and Chinese
- * remaindering.  For each descriptor: a has na, b has nb uint32 coefficients
- * (device), out receives na + nb - 1 uint64 coefficients (device).  The
- * product is exact when every coefficient of a*b is below
- * 998244353 * 754974721 * 167772161 (about 2^86.7) and below 2^64, e.g. for
- * coefficients below 2^20 and min(na, nb) <= 2^24.  Each product is padded to
- * L = 2 * nextpow2(max(na, nb)) <= 2^23.  The whole batch runs as one
- * persistent kernel launch per phase with tile schedules taken from the
- * context's tuning table (hntt_autotune).  Workspace is held by the context.
- * flags: HNTT_PLAIN.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+/* Exact integer polynomial products (the application named in Section 1)
+ * through three NTT primes, q1 = 998244353, q2 = 754974721, q3 = 167772161, and
+ * Chinese remaindering (Garner).  For each descriptor: a has na >= 1 and b has
+ * nb >= 1 uint32 coefficients (device, 4-byte aligned), out receives the
+ * na + nb - 1 coefficients of a*b as uint64 (device, 8-byte aligned).  Each
+ * product is zero-padded to L = 2 * nextpow2(max(na, nb)) <= 2^23 and
+ * computed as forward NTTs of a and b mod each q_k, a pointwise product, an
+ * inverse NTT, and CRT.  The result is the exact integer when every product
+ * coefficient is below 2^64 (it is always below q1 q2 q3 ~ 2^86.7 for
+ * coefficients below 2^20 and min(na, nb) <= 2^23; it is then returned mod
+ * 2^64 if it exceeds 2^64).  Products of any mix of lengths run together: the
+ * lengths are grouped into classes, each class's transforms for all three
+ * primes go through the same pass launches (per-transform prime slots), and
+ * operand preparation, pointwise products and CRT run as persistent kernels
+ * over the whole batch.
+ * flags: HNTT_PLAIN (fully reducing butterflies), HNTT_NO_GRAPH (enqueue the
+ * kernels directly instead of replaying a recorded HIP graph).
+ * Errors: EINVAL (NULL/misaligned pointer, empty operand), EUNSUPPORTED
+ * (padded length above 2^23), ENOMEM, EDEVICE. */
 typedef struct {
   const uint32_t *a;
   const uint32_t *b;
@@ -142,7 +150,36 @@ typedef struct {
   uint32_t na;
   uint32_t nb;
 } hntt_poly_desc;
+
+#define HNTT_NO_GRAPH 0x4u
+
+/* One-shot form: plans (reusing the previous plan of this context when the
+ * descriptors are identical) and executes on `stream`.  The context owns the
+ * plan's workspace. */
 int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream);
+
+/* Plan / execute form, for callers that keep several batches in flight.
+ * hntt_polymul_plan_create checks the descriptors on the host, builds the
+ * twiddle tables it needs (cached on the context), lays out the workspace and
+ * uploads the plan's metadata on `stream`.  The workspace is either supplied by
+ * the caller (`workspace`, `workspace_bytes`: device memory, 256-byte aligned,
+ * at least hntt_polymul_plan_workspace_bytes of the plan — pass NULL first to
+ * learn the size) or allocated by the plan (workspace = NULL).  The descriptor
+ * pointers are captured: the operands must stay valid until execution ends.
+ * hntt_polymul_plan_execute enqueues only kernel launches (no allocation, no
+ * copies, no synchronisation), so it may itself be captured; unless
+ * HNTT_NO_GRAPH was given, the launches are recorded into a HIP graph on the
+ * first execution and the graph is replayed on `stream` afterwards.  Two
+ * executions of one plan must not overlap (they share the workspace).
+ * hntt_polymul_plan_destroy frees what the plan owns; the caller must make sure
+ * no enqueued execution still uses it.
+ * Errors as for hntt_polymul_crt; ENOMEM if the given workspace is too small. */
+typedef struct hntt_polymul_plan hntt_polymul_plan;
+int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *workspace,
+                             size_t workspace_bytes, void *stream, hntt_polymul_plan **out);
+size_t hntt_polymul_plan_workspace_bytes(const hntt_polymul_plan *plan);
+int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *plan, void *stream);
+void hntt_polymul_plan_destroy(hntt_polymul_plan *plan);
 
 /* ---------------------------------------------------------------------------
  * Host-side number theory (no device needed).  These are the parameters of

@@ -55,6 +55,7 @@ def _declare(lib):
         "oracle_crt3": (None, [_p64, _p64, _p64, _p64, ctypes.c_size_t, _u64, _u64, _u64]),
         "oracle_schoolbook": (None, [_p64, ctypes.c_size_t, _p64, ctypes.c_size_t, _p64]),
         "oracle_product_coeff": (_u64, [_p64, ctypes.c_size_t, _p64, ctypes.c_size_t, ctypes.c_size_t]),
+        "oracle_poly_eval": (_u64, [_p64, ctypes.c_size_t, _u64, _u64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -172,6 +173,11 @@ class Oracle:
         c = np.empty(a.size + b.size - 1, dtype=np.uint64)
         self.lib.oracle_schoolbook(_ptr(a), a.size, _ptr(b), b.size, _ptr(c))
         return c
+
+    def poly_eval(self, c, r: int, m: int) -> int:
+        """c(r) mod m by Horner's rule."""
+        c = _u64arr(c)
+        return int(self.lib.oracle_poly_eval(_ptr(c), c.size, r, m))
 
     def product_coeff(self, a, b, k: int) -> int:
         a = _u64arr(a)

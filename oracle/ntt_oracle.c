@@ -20,7 +20,7 @@
  *     butterfly (X, Y) -> (X + W Y, X - W Y)                  (Section 4, first paragraph)
  *   - the problem setting: p prime, L = 2^l divides p - 1     (Section 1)
  *
- * Parity pins for every function live in tests/test_oracle_pins.py; no
+ * Parity pins for every function live in tests/oracle_pins.py; no
  * function here is "parity unpinned".
  */
 #include <stdint.h>
@@ -282,5 +282,14 @@ uint64_t oracle_product_coeff(const uint64_t *a, size_t na, const uint64_t *b, s
   size_t lo = (k + 1 > nb) ? k + 1 - nb : 0;
   size_t hi = (k < na - 1) ? k : na - 1;
   for (size_t i = lo; i <= hi; ++i) acc += a[i] * b[k - i];
+  return acc;
+}
+
+/* p(r) mod m for the polynomial with coefficients c[0..n) (Horner's rule), for
+ * checking long products by evaluation at a random point (Schwartz-Zippel):
+ * (a b)(r) = a(r) b(r) mod m. */
+uint64_t oracle_poly_eval(const uint64_t *c, size_t n, uint64_t r, uint64_t m) {
+  uint64_t acc = 0;
+  for (size_t i = n; i-- > 0;) acc = add_mod(mul_mod(acc, r % m, m), c[i] % m, m);
   return acc;
 }

@@ -138,8 +138,9 @@ Plan make_plan(int l, int word_bits) {
     const size_t b = pass_lds_bytes(pp);
     return pass_split(n, word_bits).kh == 0 || (b && b <= 80 * 1024);
   };
-  // column pass: adjacent columns per workgroup so that each row segment is 64 bytes
-  int g = word_bits == 32 ? 16 : 8;
+  // column pass: adjacent columns per workgroup so that each row segment is at least 64
+  // bytes, and at least 256 threads when the column transforms are short
+  int g = std::max(word_bits == 32 ? 16 : 8, 256 / pass_tpt(pl.r, word_bits));
   while (g > 1 && (pass_tpt(pl.r, word_bits) * g > kMaxPassThreads || g > (1 << pl.c) || !lds_ok(pl.r, g))) g >>= 1;
   pl.g_cols = g;
   // row pass: up to 512 threads per workgroup (the fastest row-pass shape measured at L = 2^20)
@@ -436,6 +437,7 @@ void hntt_destroy(hntt_ctx *ctx) {
   if (!ctx) return;
   if (ctx->device_ready) {
     DeviceGuard guard(ctx->device);
+    ctx->release_poly_cache();
     ctx->release_device_state();
     ctx->buffers.clear();
   }

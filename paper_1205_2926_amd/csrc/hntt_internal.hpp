@@ -56,6 +56,8 @@ struct TraceAcc {
 };
 }  // namespace hntt
 
+struct hntt_polymul_plan;
+
 struct hntt_ctx {
   int device = 0;
   size_t budget = 0;
@@ -66,6 +68,8 @@ struct hntt_ctx {
   std::map<std::tuple<uint64_t, uint64_t, int, int>, hntt::Tables> tables;
   std::map<std::pair<int, int>, hntt_tuning> tuning;  // (log2_len, word_bits) -> schedule override
   std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
+  hntt_polymul_plan *poly_cache = nullptr;  // last plan of hntt_polymul_crt
+  void release_poly_cache();
   bool trace = false;
   std::vector<hntt::TraceEvent> trace_pending;
   std::map<std::string, hntt::TraceAcc> trace_acc;

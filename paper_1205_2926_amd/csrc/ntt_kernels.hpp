@@ -13,6 +13,25 @@ struct BatchPtrs {
   uint64_t ptr[kMaxBatchPerLaunch];
 };
 
+// A transform listed in a device-side table (batched polynomial products): its data
+// pointer and the slot of its prime in the launch's PassParams::slots.
+struct XformEntry {
+  uint64_t ptr;
+  uint32_t slot;
+  uint32_t reserved;
+};
+
+constexpr int kMaxSlots = 4;
+
+// Per-prime launch parameters (tables built for the launch's sub-transform length).
+struct SlotParams {
+  uint64_t p;
+  const void *tw;     // per-stage (W, W') pairs of omega_N^(+-j)
+  const void *tt;     // kCols: split twiddles, same shape as the data
+  uint64_t scale_w;   // kWhole inverse: L^-1 and its Shoup constant
+  uint64_t scale_wp;
+};
+
 // Which pass of the transform a launch performs.
 enum class PassKind : int {
   kWhole = 0,  // the whole transform of length 2^n inside one workgroup
@@ -58,12 +77,17 @@ struct PassParams {
   int n;           // log2 of the sub-transform length handled inside a workgroup
   int log_other;   // kRows: log2(#rows) ; kCols: log2(#columns) ; kWhole: 0
   int group;       // sub-transforms per workgroup
-  int nbatch;      // transforms in this launch (<= kMaxBatchPerLaunch)
+  int nbatch;      // transforms in this launch (<= kMaxBatchPerLaunch unless `table` is set)
   uint64_t p;
   const void *tw;     // interleaved (W, W') pairs of omega_N^(+-j), j < 2^(n-1)
   const void *tt;     // kCols: interleaved split twiddles, same shape as the data
   uint64_t scale_w;   // kWhole inverse: L^-1 and its Shoup constant
   uint64_t scale_wp;
+  // Batched form: transforms listed in a device table, each with its prime's slot;
+  // when `table` is set, p/tw/tt/scale above are ignored and slots[] is used.
+  const XformEntry *table;
+  int nslots;
+  SlotParams slots[kMaxSlots];
 };
 
 hipError_t launch_pass_u32_fwd(const PassParams &pp, const BatchPtrs &ptrs, hipStream_t stream);

@@ -153,16 +153,16 @@ __device__ __forceinline__ T reduce_final(T x, T p) {
 }
 
 struct KernelArgs {
-  BatchPtrs ptrs;
+  BatchPtrs ptrs;             // transforms (slot 0) when `table` is null
+  const XformEntry *table;    // else: device table of (pointer, prime slot)
   int nbatch;
-  int log_other;  // rows: log2(#rows); cols: log2(#columns)
-  int group;      // G
-  int normalize;  // reduce the final output to [0,p)
-  int scale;      // whole inverse: multiply by L^-1 (scale_w, scale_wp)
-  uint64_t p;
-  uint64_t scale_w, scale_wp;
-  const void *tw;  // per-stage table of (W, W') pairs, entry (1 << b) + k = omega_N^(+-(k << (n-1-b)))
-  const void *tt;  // cols: interleaved split twiddles laid out like the data
+  int units;                  // tiles per transform
+  int total_tiles;            // nbatch * units
+  int log_other;              // rows: log2(#rows); cols: log2(#columns)
+  int group;                  // G
+  int normalize;              // reduce the final output to [0,p)
+  int scale;                  // whole inverse: multiply by L^-1 (slot scale_w, scale_wp)
+  SlotParams slots[kMaxSlots];
 };
 
 // What happens to a word on its way in from HBM and out to HBM.
@@ -267,26 +267,10 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   constexpr int N = 1 << N_LOG;
   constexpr int KMAX = KH > KL ? (KH > KM ? KH : KM) : (KL > KM ? KL : KM);
   constexpr int TPT = 1 << (N_LOG - KMAX);
+  static_assert(KH > 0 || KM == 0, "a single round has no middle round");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const T p = (T)a.p, p2 = p + p;
+  const int units = a.units;
   const int G = a.group;
-  const HNTT_GLOBAL Tw2 *__restrict__ twg = (const HNTT_GLOBAL Tw2 *)(a.tw);
-
-  // block -> (transform b, unit): blocks are dealt to the 8 XCDs round-robin.  Each
-  // XCD takes a contiguous eighth of the units for every transform, units fastest:
-  // neighbouring column groups (which share 128-byte lines) then run together in one
-  // L2, and an XCD re-reads only its own eighth of the split twiddles.
-  const int units = (int)(gridDim.x / a.nbatch);
-  int b, unit;
-  if ((units & 7) == 0) {
-    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, per = units >> 3;
-    unit = x * per + j % per;
-    b = j / per;
-  } else {
-    unit = blockIdx.x % units;
-    b = blockIdx.x / units;
-  }
-
   int g, t;
   if constexpr (Cols) {
     g = threadIdx.x % G;
@@ -295,47 +279,80 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     t = threadIdx.x % TPT;
     g = threadIdx.x / TPT;
   }
-  HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(a.ptrs.ptr[b]);
   const size_t C = (size_t)1 << a.log_other;
-  Edge<Lazy, Cols> edge{p, a.normalize, a.scale, (T)a.scale_w, (T)a.scale_wp, nullptr, C};
-  GlobalIO<Lazy, Cols> gio;
-  if constexpr (Cols) {
-    const size_t col = (size_t)unit * G + g;
-    gio.gsub = gbase + col;
-    gio.stride = C;
-    edge.tt = (const HNTT_GLOBAL Tw2 *)(a.tt) + col;
-  } else {
-    gio.gsub = gbase + ((size_t)unit * G + g) * N;
-    gio.stride = 1;
-  }
-  gio.edge = edge;
+  Tw2 *tws = reinterpret_cast<Tw2 *>(smem_raw);
+  T *tile = reinterpret_cast<T *>(tws + N);
 
-  static_assert(KH > 0 || KM == 0, "a single round has no middle round");
-  if constexpr (KH == 0) {
-    // one round, HBM to HBM
-    round_k<Lazy, N_LOG, KL, true>(0, t, TPT, nullptr, twg, p, p2, gio, gio);
-  } else {
-    Tw2 *tws = reinterpret_cast<Tw2 *>(smem_raw);
-    T *tile = reinterpret_cast<T *>(tws + N);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = twg[i];
-    const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
-    if constexpr (!kInverse) {
-      __syncthreads();  // twiddle table staged
-      round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, gio, lio);
-      __syncthreads();
-      if constexpr (KM > 0) {
-        round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
-        __syncthreads();
-      }
-      round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, gio);
+  // One tile (transform b, unit) per workgroup.  Blocks are dealt to the 8 XCDs
+  // round-robin; each XCD takes a contiguous eighth of the units for every transform,
+  // units fastest: neighbouring column groups (which share 128-byte lines) then run
+  // together in one L2, and an XCD re-reads only its own eighth of the split twiddles.
+  {
+    const int tl = blockIdx.x;
+    int b, unit;
+    if ((units & 7) == 0) {
+      const int x = tl & 7, j = tl >> 3, per = units >> 3;
+      unit = x * per + j % per;
+      b = j / per;
     } else {
-      round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, gio, lio);
-      __syncthreads();  // tile and twiddle table complete
-      if constexpr (KM > 0) {
-        round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
+      unit = tl % units;
+      b = tl / units;
+    }
+    int slot = 0;
+    uint64_t ptr;
+    if (a.table) {
+      ptr = a.table[b].ptr;
+      slot = (int)a.table[b].slot;
+    } else {
+      ptr = a.ptrs.ptr[b];
+    }
+    // select the slot with uniform branches (indexing the kernel-argument array with
+    // a runtime value would copy it to scratch memory)
+    SlotParams sp = a.slots[0];
+    if (slot == 1) sp = a.slots[1];
+    else if (slot == 2) sp = a.slots[2];
+    else if (slot == 3) sp = a.slots[3];
+    const T p = (T)sp.p, p2 = p + p;
+    const HNTT_GLOBAL Tw2 *__restrict__ twg = (const HNTT_GLOBAL Tw2 *)(sp.tw);
+
+    HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(ptr);
+    Edge<Lazy, Cols> edge{p, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, nullptr, C};
+    GlobalIO<Lazy, Cols> gio;
+    if constexpr (Cols) {
+      const size_t col = (size_t)unit * G + g;
+      gio.gsub = gbase + col;
+      gio.stride = C;
+      edge.tt = (const HNTT_GLOBAL Tw2 *)(sp.tt) + col;
+    } else {
+      gio.gsub = gbase + ((size_t)unit * G + g) * N;
+      gio.stride = 1;
+    }
+    gio.edge = edge;
+
+    if constexpr (KH == 0) {
+      // one round, HBM to HBM
+      round_k<Lazy, N_LOG, KL, true>(0, t, TPT, nullptr, twg, p, p2, gio, gio);
+    } else {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = twg[i];
+      const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
+      if constexpr (!kInverse) {
+        __syncthreads();  // twiddle table staged
+        round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, gio, lio);
         __syncthreads();
+        if constexpr (KM > 0) {
+          round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
+          __syncthreads();
+        }
+        round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, gio);
+      } else {
+        round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, gio, lio);
+        __syncthreads();  // tile and twiddle table complete
+        if constexpr (KM > 0) {
+          round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
+          __syncthreads();
+        }
+        round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, lio, gio);
       }
-      round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, lio, gio);
     }
   }
 }
@@ -403,23 +420,30 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   const bool cols = pp.kind == PassKind::kCols;
   const int log_other = pp.kind == PassKind::kWhole ? 0 : pp.log_other;
   const int units = (1 << log_other) / pp.group;
-  if (units < 1 || pp.nbatch < 1 || pp.nbatch > kMaxBatchPerLaunch) return hipErrorInvalidValue;
+  if (units < 1 || pp.nbatch < 1) return hipErrorInvalidValue;
+  if (!pp.table && pp.nbatch > kMaxBatchPerLaunch) return hipErrorInvalidValue;
+  if (pp.table && (pp.nslots < 1 || pp.nslots > kMaxSlots)) return hipErrorInvalidValue;
   const int threads = pass_tpt(n, HNTT_WORD) * pp.group;
   const size_t lds = pass_lds_bytes(pp);
   if (threads > kMaxPassThreads || (lds == 0 && pass_split(n, HNTT_WORD).kh > 0)) return hipErrorInvalidValue;
+  const long long total = (long long)units * pp.nbatch;
+  if (total > (1ll << 30)) return hipErrorInvalidValue;
   HNTT_NS::KernelArgs a{};
   a.ptrs = ptrs;
+  a.table = pp.table;
   a.nbatch = pp.nbatch;
+  a.units = units;
+  a.total_tiles = (int)total;
   a.log_other = log_other;
   a.group = pp.group;
   a.normalize = pp.normalize ? 1 : 0;
   a.scale = (pp.kind == PassKind::kWhole && pp.inverse) ? 1 : 0;
-  a.p = pp.p;
-  a.scale_w = pp.scale_w;
-  a.scale_wp = pp.scale_wp;
-  a.tw = pp.tw;
-  a.tt = pp.tt;
-  const int blocks = units * pp.nbatch;
+  if (pp.table) {
+    for (int i = 0; i < pp.nslots; ++i) a.slots[i] = pp.slots[i];
+  } else {
+    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp};
+  }
+  const int blocks = (int)total;
   using namespace HNTT_NS;
   if (pp.lazy) return cols ? dispatch_n<true, true>(n, a, blocks, threads, lds, stream)
                            : dispatch_n<true, false>(n, a, blocks, threads, lds, stream);

@@ -1,10 +1,413 @@
-// Exact polynomial products through three NTT primes and Chinese remaindering.
+// Exact polynomial products through three NTT primes and Chinese remaindering
+// (the application named in Section 1 of the paper): host planning, device
+// metadata, and the capture-safe enqueue that is recorded once into a HIP graph
+// and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <vector>
+
 #include "hntt.h"
 #include "hntt_internal.hpp"
+#include "ntt_kernels.hpp"
+#include "numtheory.hpp"
+#include "polymul_kernels.hpp"
 
-extern "C" int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream) {
-  (void)descs; (void)n; (void)flags; (void)stream;
+using namespace hntt;
+
+namespace {
+
+constexpr uint64_t kPrimes[3] = {998244353ull, 754974721ull, 167772161ull};
+constexpr int kMaxPolyLog = 23;  // 2^23 divides q - 1 for all three primes
+constexpr int kChunkWords = 1024;
+
+int perr(hntt_ctx *ctx, int status, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int perr(hntt_ctx *ctx, int status, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return status;
+}
+
+int hip_err(hntt_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return HNTT_OK;
+  return perr(ctx, e == hipErrorOutOfMemory ? HNTT_ENOMEM : HNTT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+uint32_t inv_mod_2_32(uint32_t q) {  // q^-1 mod 2^32 (q odd), Newton iteration
+  uint32_t x = q;
+  for (int i = 0; i < 5; ++i) x *= 2u - q * x;
+  return x;
+}
+
+uint32_t shoup32(uint64_t w, uint64_t q) { return (uint32_t)shoup_constant(w, q, 32); }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int log2_padded(uint32_t na, uint32_t nb) {
+  const uint32_t m = std::max(na, nb);
+  int l = 0;
+  while ((1u << l) < m) ++l;
+  return l + 1;  // L = 2 * nextpow2(max(na, nb))
+}
+
+struct ClassWork {
+  int l;
+  int nfwd, ninv;
+  const XformEntry *fwd, *inv;  // device tables inside the arena
+  const Tables *tab[3];
+};
+
+}  // namespace
+
+struct hntt_polymul_plan {
+  hntt_ctx *ctx = nullptr;
+  uint32_t flags = 0;
+  size_t n = 0;
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  bool owns_arena = false;
+  PolyArgs args{};
+  std::vector<ClassWork> classes;
+  std::vector<unsigned char> host_meta;  // kept alive until the plan is destroyed
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool graph_failed = false;
+  std::vector<hntt_poly_desc> descs;  // for the one-shot cache
+};
+
+namespace hntt {
+
+// Enqueue one direction of the transforms of a length class (device table of entries).
+static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t flags, hipStream_t s) {
+  const Plan plan = effective_plan(ctx, cw.l, 32);
+  const XformEntry *table = inverse ? cw.inv : cw.fwd;
+  const int count = inverse ? cw.ninv : cw.nfwd;
+  if (count == 0) return HNTT_OK;
+  PassParams base{};
+  base.word_bits = 32;
+  base.lazy = !(flags & HNTT_PLAIN);
+  base.inverse = inverse;
+  base.nbatch = count;
+  base.table = table;
+  base.nslots = 3;
+  auto slots_for = [&](PassParams &pp, int which) {
+    for (int k = 0; k < 3; ++k) {
+      const Tables &t = *cw.tab[k];
+      SlotParams &sp = pp.slots[k];
+      sp.p = kPrimes[k];
+      sp.scale_w = t.linv;
+      sp.scale_wp = t.linv_p;
+      sp.tt = nullptr;
+      if (which == 0) sp.tw = inverse ? t.inv : t.fwd;               // whole
+      else if (which == 1) {                                          // columns
+        sp.tw = inverse ? t.inv : t.fwd;
+        sp.tt = inverse ? t.tt_inv : t.tt_fwd;
+      } else sp.tw = inverse ? t.row_inv : t.row_fwd;                 // rows
+    }
+  };
+  hipError_t e;
+  if (!plan.split) {
+    PassParams pp = base;
+    pp.kind = PassKind::kWhole;
+    pp.n = cw.l;
+    pp.log_other = 0;
+    pp.group = 1;
+    pp.normalize = true;
+    slots_for(pp, 0);
+    if ((e = launch_pass(pp, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly whole)");
+    return HNTT_OK;
+  }
+  PassParams cols = base, rows = base;
+  cols.kind = PassKind::kCols;
+  cols.n = plan.r;
+  cols.log_other = plan.c;
+  cols.group = plan.g_cols;
+  slots_for(cols, 1);
+  rows.kind = PassKind::kRows;
+  rows.n = plan.c;
+  rows.log_other = plan.r;
+  rows.group = plan.g_rows;
+  slots_for(rows, 2);
+  cols.normalize = inverse;
+  rows.normalize = !inverse;
+  if (!inverse) {
+    if ((e = launch_pass(cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
+    if ((e = launch_pass(rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
+  } else {
+    if ((e = launch_pass(rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
+    if ((e = launch_pass(cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
+  }
+  return HNTT_OK;
+}
+
+static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s) {
+  hntt_ctx *ctx = pl->ctx;
+  hipError_t e;
+  int rc;
+  if ((e = launch_poly_prep(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly prep)");
+  for (const ClassWork &cw : pl->classes)
+    if ((rc = run_class(ctx, cw, false, pl->flags, s))) return rc;
+  if ((e = launch_poly_pointwise(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly pointwise)");
+  for (const ClassWork &cw : pl->classes)
+    if ((rc = run_class(ctx, cw, true, pl->flags, s))) return rc;
+  if ((e = launch_poly_crt(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly crt)");
+  return HNTT_OK;
+}
+
+}  // namespace hntt
+
+extern "C" {
+
+int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *workspace,
+                             size_t workspace_bytes, void *stream, hntt_polymul_plan **out) {
+  if (!ctx || !out) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  *out = nullptr;
+  if (n && !descs) return perr(ctx, HNTT_EINVAL, "descs is NULL");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_GRAPH)) return perr(ctx, HNTT_EINVAL, "unknown flag bits");
+  if (n > (1u << 24)) return perr(ctx, HNTT_EUNSUPPORTED, "too many products in one plan");
+  // host checks first: nothing touches the device before every descriptor is valid
+  std::vector<int> logs(n);
+  size_t ws_words = 0, chunks_ws = 0, chunks_out = 0;
+  std::vector<int> class_count(kMaxPolyLog + 1, 0);
+  for (size_t i = 0; i < n; ++i) {
+    const hntt_poly_desc &d = descs[i];
+    if (d.na == 0 || d.nb == 0) return perr(ctx, HNTT_EINVAL, "product %zu: empty operand", i);
+    if (!d.a || !d.b || !d.out) return perr(ctx, HNTT_EINVAL, "product %zu: NULL pointer", i);
+    if ((reinterpret_cast<uintptr_t>(d.a) | reinterpret_cast<uintptr_t>(d.b)) % 4 ||
+        reinterpret_cast<uintptr_t>(d.out) % 8)
+      return perr(ctx, HNTT_EINVAL, "product %zu: misaligned pointer", i);
+    const int l = log2_padded(d.na, d.nb);
+    if (l > kMaxPolyLog) return perr(ctx, HNTT_EUNSUPPORTED, "product %zu: padded length 2^%d above 2^%d", i, l,
+                                     kMaxPolyLog);
+    logs[i] = l;
+    ws_words += 6ull << l;
+    chunks_ws += ((1ull << l) + kChunkWords - 1) / kChunkWords;
+    chunks_out += ((uint64_t)d.na + d.nb - 1 + kChunkWords - 1) / kChunkWords;
+    class_count[l]++;
+  }
+  if (chunks_ws > (1u << 30) || chunks_out > (1u << 30)) return perr(ctx, HNTT_EUNSUPPORTED, "batch too large");
+  int rc = ensure_device(ctx);
+  if (rc) return rc;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(ctx->device) != hipSuccess) return perr(ctx, HNTT_EDEVICE, "hipSetDevice failed");
+  struct Restore {
+    int d;
+    ~Restore() {
+      if (d >= 0) (void)hipSetDevice(d);
+    }
+  } restore{prev};
+
+  std::unique_ptr<hntt_polymul_plan> pl(new hntt_polymul_plan());
+  pl->ctx = ctx;
+  pl->flags = flags;
+  pl->n = n;
+  pl->descs.assign(descs, descs + n);
+
+  // twiddle tables of every (prime, length) that occurs; built on the host, cached on the context
+  std::vector<ClassWork> classes;
+  for (int l = 1; l <= kMaxPolyLog; ++l) {
+    if (!class_count[l]) continue;
+    ClassWork cw{};
+    cw.l = l;
+    for (int k = 0; k < 3; ++k) {
+      const uint64_t q = kPrimes[k];
+      const uint64_t omega = powmod(primitive_root(q), (q - 1) >> l, q);
+      if ((rc = get_tables(ctx, q, omega, l, 32, &cw.tab[k]))) return rc;
+    }
+    classes.push_back(cw);
+  }
+
+  // arena: workspace, then the metadata tables
+  const size_t off_pairs = align_up(ws_words * 4, 256);
+  const size_t off_cws = align_up(off_pairs + n * sizeof(PolyPair), 256);
+  const size_t off_cout = align_up(off_cws + chunks_ws * sizeof(ChunkEntry), 256);
+  const size_t off_xf = align_up(off_cout + chunks_out * sizeof(ChunkEntry), 256);
+  size_t n_xf = 0;
+  for (const ClassWork &cw : classes) n_xf += (size_t)class_count[cw.l] * 9;
+  const size_t total = align_up(off_xf + n_xf * sizeof(XformEntry), 256);
+  if (workspace) {
+    if (workspace_bytes < total)
+      return perr(ctx, HNTT_ENOMEM, "workspace of %zu bytes is smaller than the %zu this plan needs", workspace_bytes,
+                  total);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return perr(ctx, HNTT_EINVAL, "workspace not 256-byte aligned");
+    pl->arena = static_cast<char *>(workspace);
+    pl->owns_arena = false;
+  } else {
+    if (ctx->budget && ctx->bytes_held + total > ctx->budget)
+      return perr(ctx, HNTT_ENOMEM, "memory budget of %zu bytes exceeded (plan needs %zu)", ctx->budget, total);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, total);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMalloc(polymul workspace)");
+    pl->arena = static_cast<char *>(p);
+    pl->owns_arena = true;
+    ctx->bytes_held += total;
+  }
+  pl->arena_bytes = total;
+
+  // host images of the metadata
+  std::vector<unsigned char> &meta = pl->host_meta;
+  meta.assign(total - off_pairs, 0);
+  PolyPair *hp = reinterpret_cast<PolyPair *>(meta.data());
+  ChunkEntry *hcw = reinterpret_cast<ChunkEntry *>(meta.data() + (off_cws - off_pairs));
+  ChunkEntry *hco = reinterpret_cast<ChunkEntry *>(meta.data() + (off_cout - off_pairs));
+  XformEntry *hxf = reinterpret_cast<XformEntry *>(meta.data() + (off_xf - off_pairs));
+  uint32_t *ws_dev = reinterpret_cast<uint32_t *>(pl->arena);
+  size_t woff = 0, cw_i = 0, co_i = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const hntt_poly_desc &d = descs[i];
+    const int l = logs[i];
+    hp[i] = PolyPair{d.a, d.b, d.out, d.na, d.nb, (uint32_t)l, 0, woff};
+    for (uint64_t s = 0; s < (1ull << l); s += kChunkWords) hcw[cw_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
+    for (uint64_t s = 0; s < (uint64_t)d.na + d.nb - 1; s += kChunkWords) hco[co_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
+    woff += 6ull << l;
+  }
+  // transform tables per length class: forward over A_k and B_k, inverse over A_k
+  size_t xi = 0;
+  const XformEntry *dxf = reinterpret_cast<const XformEntry *>(pl->arena + off_xf);
+  for (ClassWork &cw : classes) {
+    const size_t f0 = xi;
+    for (size_t i = 0; i < n; ++i) {
+      if (logs[i] != cw.l) continue;
+      const uint64_t L = 1ull << cw.l;
+      for (int k = 0; k < 3; ++k) {
+        hxf[xi++] = XformEntry{reinterpret_cast<uint64_t>(ws_dev + hp[i].ws_off + (2 * k) * L), (uint32_t)k, 0};
+        hxf[xi++] = XformEntry{reinterpret_cast<uint64_t>(ws_dev + hp[i].ws_off + (2 * k + 1) * L), (uint32_t)k, 0};
+      }
+    }
+    cw.fwd = dxf + f0;
+    cw.nfwd = (int)(xi - f0);
+    const size_t i0 = xi;
+    for (size_t i = 0; i < n; ++i) {
+      if (logs[i] != cw.l) continue;
+      const uint64_t L = 1ull << cw.l;
+      for (int k = 0; k < 3; ++k)
+        hxf[xi++] = XformEntry{reinterpret_cast<uint64_t>(ws_dev + hp[i].ws_off + (2 * k) * L), (uint32_t)k, 0};
+    }
+    cw.inv = dxf + i0;
+    cw.ninv = (int)(xi - i0);
+  }
+  pl->classes = classes;
+
+  PolyArgs &a = pl->args;
+  a.pairs = reinterpret_cast<const PolyPair *>(pl->arena + off_pairs);
+  a.chunks_ws = reinterpret_cast<const ChunkEntry *>(pl->arena + off_cws);
+  a.nchunks_ws = (int)chunks_ws;
+  a.chunks_out = reinterpret_cast<const ChunkEntry *>(pl->arena + off_cout);
+  a.nchunks_out = (int)chunks_out;
+  a.workspace = ws_dev;
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t q = kPrimes[k];
+    const uint64_t r = (uint64_t)(((u128)1 << 64) % q);
+    a.primes[k] = PrimeConst{(uint32_t)q, shoup32(1, q), inv_mod_2_32((uint32_t)q), (uint32_t)r};
+  }
+  const uint64_t q1 = kPrimes[0], q2 = kPrimes[1], q3 = kPrimes[2];
+  const uint64_t c12 = powmod(q1 % q2, q2 - 2, q2), c13 = powmod(q1 % q3, q3 - 2, q3),
+                 c23 = powmod(q2 % q3, q3 - 2, q3);
+  a.crt = CrtConst{(uint32_t)c12, shoup32(c12, q2), (uint32_t)c13, shoup32(c13, q3), (uint32_t)c23, shoup32(c23, q3)};
+
+  // upload the metadata in stream order (the copy is staged before this call returns)
+  hipError_t e = hipMemcpyAsync(pl->arena + off_pairs, meta.data(), meta.size(), hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) {
+    int r = hip_err(ctx, e, "hipMemcpyAsync(polymul metadata)");
+    hntt_polymul_plan_destroy(pl.release());
+    return r;
+  }
+  *out = pl.release();
+  return HNTT_OK;
+}
+
+size_t hntt_polymul_plan_workspace_bytes(const hntt_polymul_plan *plan) { return plan ? plan->arena_bytes : 0; }
+
+int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *pl, void *stream) {
+  if (!ctx || !pl || pl->ctx != ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (pl->n == 0) return HNTT_OK;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(ctx->device) != hipSuccess) return perr(ctx, HNTT_EDEVICE, "hipSetDevice failed");
+  struct Restore {
+    int d;
+    ~Restore() {
+      if (d >= 0) (void)hipSetDevice(d);
+    }
+  } restore{prev};
+  hipStream_t s = (hipStream_t)stream;
+  const bool use_graph = !(pl->flags & HNTT_NO_GRAPH) && !pl->graph_failed && !ctx->trace;
+  if (!use_graph) return enqueue_plan(pl, s);
+  if (!pl->exec) {
+    // record every launch once on a private stream, then replay the graph on the caller's stream
+    hipStream_t cs = nullptr;
+    bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
+    int rc = ok ? enqueue_plan(pl, cs) : HNTT_EDEVICE;
+    hipGraph_t g = nullptr;
+    if (ok) ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == HNTT_OK;
+    if (ok) ok = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (cs) (void)hipStreamDestroy(cs);
+    if (!ok) {
+      if (g) (void)hipGraphDestroy(g);
+      pl->exec = nullptr;
+      pl->graph_failed = true;
+      (void)hipGetLastError();
+      ctx->last_error.clear();
+      return enqueue_plan(pl, s);
+    }
+    pl->graph = g;
+  }
+  return hip_err(ctx, hipGraphLaunch(pl->exec, s), "hipGraphLaunch(polymul)");
+}
+
+void hntt_polymul_plan_destroy(hntt_polymul_plan *pl) {
+  if (!pl) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->owns_arena && pl->arena) {
+    (void)hipFree(pl->arena);
+    if (pl->ctx && pl->ctx->bytes_held >= pl->arena_bytes) pl->ctx->bytes_held -= pl->arena_bytes;
+  }
+  delete pl;
+}
+
+int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream) {
   if (!ctx) return HNTT_EINVAL;
-  ctx->last_error = "hntt_polymul_crt is not built yet";
-  return HNTT_EUNSUPPORTED;
+  ctx->last_error.clear();
+  if (n == 0) return HNTT_OK;
+  if (!descs) return perr(ctx, HNTT_EINVAL, "descs is NULL");
+  // reuse the cached plan when the same products are requested again (e.g. a benchmark loop)
+  hntt_polymul_plan *pl = ctx->poly_cache;
+  const bool same = pl && pl->flags == flags && pl->n == n &&
+                    std::memcmp(pl->descs.data(), descs, n * sizeof(hntt_poly_desc)) == 0;
+  if (!same) {
+    if (pl) {
+      (void)hipStreamSynchronize((hipStream_t)stream);  // the old plan's work may still use its arena
+      hntt_polymul_plan_destroy(pl);
+      ctx->poly_cache = nullptr;
+    }
+    int rc = hntt_polymul_plan_create(ctx, descs, n, flags, nullptr, 0, stream, &pl);
+    if (rc) return rc;
+    ctx->poly_cache = pl;
+  }
+  return hntt_polymul_plan_execute(ctx, pl, stream);
+}
+
+}  // extern "C"
+
+void hntt_ctx::release_poly_cache() {
+  if (poly_cache) {
+    hntt_polymul_plan_destroy(poly_cache);
+    poly_cache = nullptr;
+  }
 }

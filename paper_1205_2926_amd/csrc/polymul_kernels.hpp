@@ -1,0 +1,55 @@
+// Device-side records and launchers of the three-prime polynomial product.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hntt {
+
+// One product of the batch.  Its workspace (ws_off words into the plan's arena)
+// holds six arrays of L = 2^log2_len words: A1, B1, A2, B2, A3, B3 (operands
+// reduced mod q_k, zero-padded, transformed in place; A_k ends as the residues
+// of the product mod q_k).
+struct PolyPair {
+  const uint32_t *a;
+  const uint32_t *b;
+  uint64_t *out;
+  uint32_t na, nb;
+  uint32_t log2_len;
+  uint32_t reserved;
+  uint64_t ws_off;
+};
+
+// A 1024-word chunk of one product's positions.
+struct ChunkEntry {
+  uint32_t pair;
+  uint32_t start;
+};
+
+// Per-prime constants: q, floor(2^32/q) (Shoup constant of 1), q^-1 mod 2^32
+// (Montgomery), 2^64 mod q.
+struct PrimeConst {
+  uint32_t q, one_p, jinv, r2;
+};
+
+// Garner constants with their Shoup constants: q1^-1 mod q2, q1^-1 mod q3, q2^-1 mod q3.
+struct CrtConst {
+  uint32_t c12, c12p, c13, c13p, c23, c23p;
+};
+
+struct PolyArgs {
+  const PolyPair *pairs;
+  const ChunkEntry *chunks_ws;   // chunks over the padded length L of every product
+  int nchunks_ws;
+  const ChunkEntry *chunks_out;  // chunks over the na + nb - 1 output coefficients
+  int nchunks_out;
+  uint32_t *workspace;
+  PrimeConst primes[3];
+  CrtConst crt;
+};
+
+hipError_t launch_poly_prep(const PolyArgs &a, hipStream_t s);
+hipError_t launch_poly_pointwise(const PolyArgs &a, hipStream_t s);
+hipError_t launch_poly_crt(const PolyArgs &a, hipStream_t s);
+
+}  // namespace hntt

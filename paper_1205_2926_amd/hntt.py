@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libhntt.so")
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5
 PLAIN = 0x1
 NO_NORMALIZE = 0x2
+NO_GRAPH = 0x4
 
 _c_u64 = ctypes.c_uint64
 _c_u32 = ctypes.c_uint32
@@ -67,6 +68,11 @@ SIGNATURES = {
     "hntt_ntt_inverse": (ctypes.c_int, [_c_vp, ctypes.POINTER(Desc), ctypes.c_size_t, _c_u32, _c_vp]),
     "hntt_pointwise_mul": (ctypes.c_int, [_c_vp, ctypes.POINTER(PwDesc), ctypes.c_size_t, _c_u32, _c_vp]),
     "hntt_polymul_crt": (ctypes.c_int, [_c_vp, ctypes.POINTER(PolyDesc), ctypes.c_size_t, _c_u32, _c_vp]),
+    "hntt_polymul_plan_create": (ctypes.c_int, [_c_vp, ctypes.POINTER(PolyDesc), ctypes.c_size_t, _c_u32, _c_vp,
+                                                ctypes.c_size_t, _c_vp, ctypes.POINTER(_c_vp)]),
+    "hntt_polymul_plan_workspace_bytes": (ctypes.c_size_t, [_c_vp]),
+    "hntt_polymul_plan_execute": (ctypes.c_int, [_c_vp, _c_vp, _c_vp]),
+    "hntt_polymul_plan_destroy": (None, [_c_vp]),
     "hntt_is_prime": (ctypes.c_int, [_c_u64]),
     "hntt_primitive_root": (_c_u64, [_c_u64]),
     "hntt_root_of_unity": (ctypes.c_int, [_c_u64, _c_u32, ctypes.POINTER(_c_u64)]),
@@ -149,6 +155,43 @@ def _stream_handle(stream, device) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
+class PolymulPlan:
+    """A planned batch of products (hntt_polymul_plan_*); execute() enqueues it, destroy() frees it."""
+
+    def __init__(self, ctx, pairs, outs, plain, graph, workspace, stream):
+        self.ctx = ctx
+        self.arr = ctx.poly_descs(pairs, outs)
+        self.keep = (list(pairs), list(outs), workspace)
+        flags = (PLAIN if plain else 0) | (0 if graph else NO_GRAPH)
+        h = _c_vp()
+        dev = outs[0].device if outs else torch.device("cuda", ctx.device)
+        ws_ptr = workspace.data_ptr() if workspace is not None else None
+        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        ctx._check(ctx.lib.hntt_polymul_plan_create(ctx.handle, self.arr, len(pairs), flags, ws_ptr, ws_bytes,
+                                                    _stream_handle(stream, dev), ctypes.byref(h)))
+        self.handle = h
+        self.device = dev
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.ctx.lib.hntt_polymul_plan_workspace_bytes(self.handle))
+
+    def execute(self, stream=None):
+        self.ctx._check(self.ctx.lib.hntt_polymul_plan_execute(self.ctx.handle, self.handle,
+                                                               _stream_handle(stream, self.device)))
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.hntt_polymul_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 class Context:
     """A library context bound to one HIP device (twiddle tables and workspaces live here)."""
 
@@ -229,15 +272,29 @@ class Context:
         self._check(self.lib.hntt_pointwise_mul(self.handle, d, 1, 0, _stream_handle(stream, a.device)))
         return c
 
-    def polymul_crt(self, pairs: Sequence[tuple[torch.Tensor, torch.Tensor]], outs: Sequence[torch.Tensor],
-                    plain: bool = False, stream=None):
+    @staticmethod
+    def poly_descs(pairs: Sequence[tuple[torch.Tensor, torch.Tensor]], outs: Sequence[torch.Tensor]):
         arr = (PolyDesc * len(pairs))()
         for i, ((a, b), o) in enumerate(zip(pairs, outs)):
+            if a.element_size() != 4 or b.element_size() != 4 or o.element_size() != 8:
+                raise TypeError("operands must be 32-bit and outputs 64-bit integer tensors")
+            if o.numel() < a.numel() + b.numel() - 1:
+                raise ValueError("output shorter than na + nb - 1")
             arr[i] = PolyDesc(a.data_ptr(), b.data_ptr(), o.data_ptr(), a.numel(), b.numel())
+        return arr
+
+    def polymul_crt(self, pairs: Sequence[tuple[torch.Tensor, torch.Tensor]], outs: Sequence[torch.Tensor],
+                    plain: bool = False, graph: bool = True, stream=None):
+        """Exact products out[i] = a_i * b_i (three primes + CRT), one call for the whole batch."""
+        arr = self.poly_descs(pairs, outs)
         dev = outs[0].device if outs else torch.device("cuda", self.device)
-        self._check(self.lib.hntt_polymul_crt(self.handle, arr, len(pairs), PLAIN if plain else 0,
-                                              _stream_handle(stream, dev)))
+        flags = (PLAIN if plain else 0) | (0 if graph else NO_GRAPH)
+        self._check(self.lib.hntt_polymul_crt(self.handle, arr, len(pairs), flags, _stream_handle(stream, dev)))
         return outs
+
+    def polymul_plan(self, pairs, outs, plain: bool = False, graph: bool = True, workspace: torch.Tensor = None,
+                     stream=None) -> "PolymulPlan":
+        return PolymulPlan(self, pairs, outs, plain, graph, workspace, stream)
 
     # -- schedule tuning ---------------------------------------------------------------------------
     def set_tuning(self, log2_len: int, word_bits: int, g_cols: int = 0, g_rows: int = 0, batch_chunk: int = 0):

@@ -304,6 +304,20 @@ def pin_polymul_exact(orc):
     assert got[n - 1] == n * ((1 << 20) - 1) ** 2 and got[0] == ((1 << 20) - 1) ** 2
 
 
+def pin_poly_eval(orc):
+    r = random.Random(25)
+    for m in ((1 << 61) - 1, 998244353, 17):
+        for n in (1, 2, 50, 300):
+            c = [r.randrange(1 << 63) for _ in range(n)]
+            x = r.randrange(1 << 62)
+            assert orc.poly_eval(c, x, m) == sum(ci * pow(x, i, m) for i, ci in enumerate(c)) % m
+    # evaluation respects products: (a b)(x) = a(x) b(x)
+    a = [r.randrange(1 << 20) for _ in range(40)]
+    b = [r.randrange(1 << 20) for _ in range(33)]
+    m, x = (1 << 61) - 1, 123456789
+    assert orc.poly_eval(_conv(a, b), x, m) == orc.poly_eval(a, x, m) * orc.poly_eval(b, x, m) % m
+
+
 ALL_PINS = [pin_golden_tiny, pin_forward_naive, pin_forward_sympy, pin_inverse_naive, pin_inverse_sympy,
             pin_roundtrip, pin_closed_forms, pin_dft_point, pin_bitrev, pin_number_theory, pin_prime_search,
-            pin_pointwise, pin_polymul_mod, pin_crt3, pin_schoolbook, pin_polymul_exact]
+            pin_pointwise, pin_polymul_mod, pin_crt3, pin_schoolbook, pin_polymul_exact, pin_poly_eval]

@@ -156,3 +156,26 @@ def test_tuning_overrides_checked_on_host(ctx):
         ctx.set_tuning(10, 32, g_cols=4)  # one-pass length has no column pass
     ctx.set_tuning(20, 32)
     assert ctx.get_plan(20, 32) == base
+
+
+def _poly(a=4096, b=8192, out=16384, na=10, nb=7):
+    return (hntt.PolyDesc * 1)(hntt.PolyDesc(a, b, out, na, nb))
+
+
+@pytest.mark.parametrize("kw,status,msg", [
+    (dict(na=0), hntt.EINVAL, "empty"),
+    (dict(a=0), hntt.EINVAL, "NULL"),
+    (dict(out=0), hntt.EINVAL, "NULL"),
+    (dict(a=4098), hntt.EINVAL, "misaligned"),
+    (dict(out=16388), hntt.EINVAL, "misaligned"),
+    (dict(na=(1 << 22) + 1), hntt.EUNSUPPORTED, "2^23"),
+])
+def test_polymul_descriptor_checks(ctx, kw, status, msg):
+    """Bad product descriptors are rejected on the host before any device call."""
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = ctx.lib.hntt_polymul_plan_create(ctx.handle, _poly(**kw), 1, 0, None, 0, None, ctypes.byref(h))
+    assert rc == status and msg in ctx.last_error(), ctx.last_error()
+    assert not h.value
+    assert ctx.lib.hntt_polymul_crt(ctx.handle, _poly(**kw), 1, 0, None) == status
+    assert ctx.lib.hntt_polymul_crt(ctx.handle, _poly(), 1, 0x80, None) == hntt.EINVAL

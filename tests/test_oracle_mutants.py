@@ -40,6 +40,8 @@ MUTANTS = [
     ("primroot_wrong_test", "== 1) ok = 0;", "== p - 1) ok = 0;", 0),
     ("bitrev_shift", "<< (l - 1 - b);", "<< (l - b);", 0),
     ("coeff_low_bound", "size_t lo = (k + 1 > nb) ? k + 1 - nb : 0;", "size_t lo = (k + 1 > nb) ? k + 1 - nb : 1;", 0),
+    ("poly_eval_drops_coeff", "acc = add_mod(mul_mod(acc, r % m, m), c[i] % m, m);",
+     "acc = mul_mod(acc, r % m, m);", 0),
     ("prime_search_step", "uint64_t c = k * step + 1;", "uint64_t c = k * step - 1;", 0),
 ]
 
