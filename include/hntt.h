@@ -178,6 +178,10 @@ typedef struct hntt_polymul_plan hntt_polymul_plan;
 int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *workspace,
                              size_t workspace_bytes, void *stream, hntt_polymul_plan **out);
 size_t hntt_polymul_plan_workspace_bytes(const hntt_polymul_plan *plan);
+/* Workspace a plan for these descriptors needs, computed on the host from the
+ * lengths alone (pointers are not read), e.g. for admission control before any
+ * device memory is committed.  Errors: EINVAL, EUNSUPPORTED. */
+int hntt_polymul_workspace_size(const hntt_poly_desc *descs, size_t n, size_t *bytes_out);
 int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *plan, void *stream);
 void hntt_polymul_plan_destroy(hntt_polymul_plan *plan);
 

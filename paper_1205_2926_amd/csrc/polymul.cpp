@@ -60,6 +60,47 @@ int log2_padded(uint32_t na, uint32_t nb) {
   return l + 1;  // L = 2 * nextpow2(max(na, nb))
 }
 
+// Sizes and arena layout of a batch (host only).
+struct Sizing {
+  std::vector<int> logs;
+  std::vector<int> class_count;
+  size_t ws_words = 0, chunks_ws = 0, chunks_out = 0;
+  size_t off_pairs = 0, off_cws = 0, off_cout = 0, off_xf = 0, total = 0;
+};
+
+int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_ptrs, Sizing *sz) {
+  sz->logs.assign(n, 0);
+  sz->class_count.assign(kMaxPolyLog + 1, 0);
+  for (size_t i = 0; i < n; ++i) {
+    const hntt_poly_desc &d = descs[i];
+    if (d.na == 0 || d.nb == 0) return perr(ctx, HNTT_EINVAL, "product %zu: empty operand", i);
+    if (check_ptrs) {
+      if (!d.a || !d.b || !d.out) return perr(ctx, HNTT_EINVAL, "product %zu: NULL pointer", i);
+      if ((reinterpret_cast<uintptr_t>(d.a) | reinterpret_cast<uintptr_t>(d.b)) % 4 ||
+          reinterpret_cast<uintptr_t>(d.out) % 8)
+        return perr(ctx, HNTT_EINVAL, "product %zu: misaligned pointer", i);
+    }
+    const int l = log2_padded(d.na, d.nb);
+    if (l > kMaxPolyLog)
+      return perr(ctx, HNTT_EUNSUPPORTED, "product %zu: padded length 2^%d above 2^%d", i, l, kMaxPolyLog);
+    sz->logs[i] = l;
+    sz->ws_words += 6ull << l;
+    sz->chunks_ws += ((1ull << l) + kChunkWords - 1) / kChunkWords;
+    sz->chunks_out += ((uint64_t)d.na + d.nb - 1 + kChunkWords - 1) / kChunkWords;
+    sz->class_count[l]++;
+  }
+  if (sz->chunks_ws > (1u << 30) || sz->chunks_out > (1u << 30))
+    return perr(ctx, HNTT_EUNSUPPORTED, "batch too large");
+  size_t n_xf = 0;
+  for (int l = 0; l <= kMaxPolyLog; ++l) n_xf += (size_t)sz->class_count[l] * 9;
+  sz->off_pairs = align_up(sz->ws_words * 4, 256);
+  sz->off_cws = align_up(sz->off_pairs + n * sizeof(PolyPair), 256);
+  sz->off_cout = align_up(sz->off_cws + sz->chunks_ws * sizeof(ChunkEntry), 256);
+  sz->off_xf = align_up(sz->off_cout + sz->chunks_out * sizeof(ChunkEntry), 256);
+  sz->total = align_up(sz->off_xf + n_xf * sizeof(XformEntry), 256);
+  return HNTT_OK;
+}
+
 struct ClassWork {
   int l;
   int nfwd, ninv;
@@ -177,27 +218,13 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
   if (flags & ~(HNTT_PLAIN | HNTT_NO_GRAPH)) return perr(ctx, HNTT_EINVAL, "unknown flag bits");
   if (n > (1u << 24)) return perr(ctx, HNTT_EUNSUPPORTED, "too many products in one plan");
   // host checks first: nothing touches the device before every descriptor is valid
-  std::vector<int> logs(n);
-  size_t ws_words = 0, chunks_ws = 0, chunks_out = 0;
-  std::vector<int> class_count(kMaxPolyLog + 1, 0);
-  for (size_t i = 0; i < n; ++i) {
-    const hntt_poly_desc &d = descs[i];
-    if (d.na == 0 || d.nb == 0) return perr(ctx, HNTT_EINVAL, "product %zu: empty operand", i);
-    if (!d.a || !d.b || !d.out) return perr(ctx, HNTT_EINVAL, "product %zu: NULL pointer", i);
-    if ((reinterpret_cast<uintptr_t>(d.a) | reinterpret_cast<uintptr_t>(d.b)) % 4 ||
-        reinterpret_cast<uintptr_t>(d.out) % 8)
-      return perr(ctx, HNTT_EINVAL, "product %zu: misaligned pointer", i);
-    const int l = log2_padded(d.na, d.nb);
-    if (l > kMaxPolyLog) return perr(ctx, HNTT_EUNSUPPORTED, "product %zu: padded length 2^%d above 2^%d", i, l,
-                                     kMaxPolyLog);
-    logs[i] = l;
-    ws_words += 6ull << l;
-    chunks_ws += ((1ull << l) + kChunkWords - 1) / kChunkWords;
-    chunks_out += ((uint64_t)d.na + d.nb - 1 + kChunkWords - 1) / kChunkWords;
-    class_count[l]++;
-  }
-  if (chunks_ws > (1u << 30) || chunks_out > (1u << 30)) return perr(ctx, HNTT_EUNSUPPORTED, "batch too large");
-  int rc = ensure_device(ctx);
+  Sizing sz;
+  int rc = size_batch(ctx, descs, n, true, &sz);
+  if (rc) return rc;
+  const std::vector<int> &logs = sz.logs;
+  const std::vector<int> &class_count = sz.class_count;
+  const size_t ws_words = sz.ws_words, chunks_ws = sz.chunks_ws, chunks_out = sz.chunks_out;
+  rc = ensure_device(ctx);
   if (rc) return rc;
   int prev = -1;
   (void)hipGetDevice(&prev);
@@ -230,13 +257,8 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
   }
 
   // arena: workspace, then the metadata tables
-  const size_t off_pairs = align_up(ws_words * 4, 256);
-  const size_t off_cws = align_up(off_pairs + n * sizeof(PolyPair), 256);
-  const size_t off_cout = align_up(off_cws + chunks_ws * sizeof(ChunkEntry), 256);
-  const size_t off_xf = align_up(off_cout + chunks_out * sizeof(ChunkEntry), 256);
-  size_t n_xf = 0;
-  for (const ClassWork &cw : classes) n_xf += (size_t)class_count[cw.l] * 9;
-  const size_t total = align_up(off_xf + n_xf * sizeof(XformEntry), 256);
+  const size_t off_pairs = sz.off_pairs, off_cws = sz.off_cws, off_cout = sz.off_cout, off_xf = sz.off_xf;
+  const size_t total = sz.total;
   if (workspace) {
     if (workspace_bytes < total)
       return perr(ctx, HNTT_ENOMEM, "workspace of %zu bytes is smaller than the %zu this plan needs", workspace_bytes,
@@ -330,6 +352,15 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
 }
 
 size_t hntt_polymul_plan_workspace_bytes(const hntt_polymul_plan *plan) { return plan ? plan->arena_bytes : 0; }
+
+int hntt_polymul_workspace_size(const hntt_poly_desc *descs, size_t n, size_t *bytes_out) {
+  if (!bytes_out || (n && !descs)) return HNTT_EINVAL;
+  Sizing sz;
+  int rc = size_batch(nullptr, descs, n, false, &sz);
+  if (rc) return rc;
+  *bytes_out = n ? sz.total : 0;
+  return HNTT_OK;
+}
 
 int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *pl, void *stream) {
   if (!ctx || !pl || pl->ctx != ctx) return HNTT_EINVAL;

@@ -72,6 +72,8 @@ SIGNATURES = {
                                                 ctypes.c_size_t, _c_vp, ctypes.POINTER(_c_vp)]),
     "hntt_polymul_plan_workspace_bytes": (ctypes.c_size_t, [_c_vp]),
     "hntt_polymul_plan_execute": (ctypes.c_int, [_c_vp, _c_vp, _c_vp]),
+    "hntt_polymul_workspace_size": (ctypes.c_int, [ctypes.POINTER(PolyDesc), ctypes.c_size_t,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
     "hntt_polymul_plan_destroy": (None, [_c_vp]),
     "hntt_is_prime": (ctypes.c_int, [_c_u64]),
     "hntt_primitive_root": (_c_u64, [_c_u64]),
@@ -134,6 +136,18 @@ def shoup_constant(w: int, p: int, word_bits: int) -> int:
     rc = load().hntt_shoup_constant(w, p, word_bits, ctypes.byref(out))
     if rc:
         raise HnttError(rc, "bad Shoup constant arguments")
+    return int(out.value)
+
+
+def polymul_workspace_size(lengths: Sequence[tuple[int, int]]) -> int:
+    """Workspace bytes of a polymul plan for products of (na, nb) coefficients (host only)."""
+    arr = (PolyDesc * len(lengths))()
+    for i, (na, nb) in enumerate(lengths):
+        arr[i] = PolyDesc(None, None, None, na, nb)
+    out = ctypes.c_size_t(0)
+    rc = load().hntt_polymul_workspace_size(arr, len(lengths), ctypes.byref(out))
+    if rc:
+        raise HnttError(rc, "bad polymul lengths")
     return int(out.value)
 
 

@@ -179,3 +179,28 @@ def test_polymul_descriptor_checks(ctx, kw, status, msg):
     assert not h.value
     assert ctx.lib.hntt_polymul_crt(ctx.handle, _poly(**kw), 1, 0, None) == status
     assert ctx.lib.hntt_polymul_crt(ctx.handle, _poly(), 1, 0x80, None) == hntt.EINVAL
+
+
+def test_polymul_workspace_size_host_only():
+    # 6 arrays of L = 2 * nextpow2(max(na, nb)) words plus metadata, no device needed
+    s = hntt.polymul_workspace_size([(1 << 20, 1 << 20)])
+    assert 6 * 4 * (1 << 21) <= s < 6 * 4 * (1 << 21) + (1 << 20)
+    assert hntt.polymul_workspace_size([(3, 5)]) >= 6 * 4 * 16
+    with pytest.raises(hntt.HnttError):
+        hntt.polymul_workspace_size([(0, 5)])
+    with pytest.raises(hntt.HnttError):
+        hntt.polymul_workspace_size([((1 << 22) + 1, 5)])
+
+
+def test_serving_arena_allocator():
+    from paper_1205_2926_amd.serve import Arena
+    a = Arena(4096)
+    x = a.alloc(1000)
+    y = a.alloc(1000)
+    z = a.alloc(2100)
+    assert x == 0 and y == 1024 and z is None
+    a.release(x, 1000)
+    assert a.alloc(1024) == 0
+    a.release(0, 1024)
+    a.release(y, 1000)
+    assert a.free == [(0, 4096)] and a.used == 0 and a.peak == 2048
