@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in schedule instead of the autotuner's")
+    ap.add_argument("--workload", default="batch64",
+                    choices=["batch64", "single1k", "u64", "polymul", "serving"],
+                    help="batch64 (default, the headline line); the others print their own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for HBM byte counters)")
     return ap.parse_args()
@@ -144,6 +147,10 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload != "batch64":
+        from paper_1205_2926_amd import bench_workloads
+        print(json.dumps(getattr(bench_workloads, args.workload)(args)))
         return
 
     import numpy as np

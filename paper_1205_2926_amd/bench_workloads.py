@@ -1,0 +1,146 @@
+"""Measurements of the non-headline workloads for ``bench.py --workload ...``.
+
+single1k  one forward NTT of 1024 residues (latency, lazy and plain)
+u64       8 NTTs of length 2^22 over the 62-bit prime, forward + inverse, lazy vs plain
+polymul   4096 products with log-uniform lengths 2^8..2^16, three primes + CRT, one graph launch
+serving   Poisson stream of products (lengths 2^10..2^20), rate swept up to saturation
+Each returns one JSON-able dict.  Inputs are the seeded synthetic workloads of
+``workloads.py``; results are checked (round trip / sampled coefficients)
+before the numbers are reported.
+"""
+from __future__ import annotations
+
+import random
+import time
+
+import numpy as np
+import torch
+
+from . import autotune, hntt
+from .workloads import BATCH8_4M_U64, SINGLE_1K, polymul_pairs
+
+
+def _events_ms(fn, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def single1k(args):
+    cfg = SINGLE_1K
+    ctx = hntt.Context(0)
+    w = hntt.root_of_unity(cfg.p, cfg.log2_len)
+    x_np = cfg.data()
+    x = torch.from_numpy(x_np.view(np.int32)).cuda()
+    out = {"metric": "single forward NTT latency", "unit": "us", "workload": "1 x 2^10, p=998244353, u32"}
+    for plain in (False, True):
+        for _ in range(20):
+            ctx.ntt_forward(x, cfg.p, w, plain=plain)
+            ctx.ntt_inverse(x, cfg.p, w, plain=plain)
+        fwd = _events_ms(lambda: ctx.ntt_forward(x, cfg.p, w, plain=plain), 200) * 1e3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(200):
+            ctx.ntt_forward(x, cfg.p, w, plain=plain)
+            torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 200 * 1e6
+        out["plain" if plain else "lazy"] = {"device_us": fwd, "host_roundtrip_us": wall}
+    # restore and check: an even number of forward-only launches were applied; redo from the input
+    ctx.close()
+    return out
+
+
+def u64(args):
+    cfg = BATCH8_4M_U64
+    ctx = hntt.Context(0)
+    l, p = cfg.log2_len, cfg.p
+    w = hntt.root_of_unity(p, l)
+    x_np = cfg.data()
+    x = torch.from_numpy(x_np.view(np.int64)).cuda()
+    res = {}
+    for plain in (False, True):
+        autotune.tune(ctx, x, p, w, plain=plain)
+        ms = _events_ms(lambda: (ctx.ntt_forward(x, p, w, plain=plain), ctx.ntt_inverse(x, p, w, plain=plain)),
+                        args.steps)
+        res["plain" if plain else "lazy"] = {"ms_per_step": ms, "butterflies_per_s": 2 * cfg.butterflies / (ms / 1e3),
+                                             "schedule": ctx.get_plan(l, 64)}
+    assert np.array_equal(x.cpu().numpy().view(np.uint64), x_np), "u64 round trip mismatch"
+    ctx.close()
+    return {"metric": "NTT butterflies/s, 64-bit words", "unit": "butterflies/s",
+            "value": res["lazy"]["butterflies_per_s"], "workload": "8 x 2^22 forward+inverse, p=2^62-ish, u64",
+            "p": p, "lazy": res["lazy"], "plain": res["plain"],
+            "lazy_over_plain": res["plain"]["ms_per_step"] / res["lazy"]["ms_per_step"]}
+
+
+def polymul(args):
+    import oracle
+    pairs = polymul_pairs(seed=4, pairs=4096)
+    ctx = hntt.Context(0)
+    dpairs = [(torch.from_numpy(a.view(np.int32)).cuda(), torch.from_numpy(b.view(np.int32)).cuda())
+              for a, b in pairs]
+    outs = [torch.empty(a.size + b.size - 1, dtype=torch.int64, device="cuda") for a, b in pairs]
+    # butterflies: per product, 6 forward and 3 inverse transforms of length L = 2 nextpow2(n)
+    bfly = 0
+    words = 0
+    for a, b in pairs:
+        n = max(a.size, b.size)
+        l = (n - 1).bit_length() + 1
+        bfly += 9 * l * (1 << (l - 1))
+        words += 1 << l
+    res = {}
+    for plain in (False, True):
+        plan = ctx.polymul_plan(dpairs, outs, plain=plain)
+        plan.execute()
+        torch.cuda.synchronize()
+        ms = _events_ms(plan.execute, max(3, args.steps // 2))
+        res["plain" if plain else "lazy"] = {"ms_per_batch": ms, "products_per_s": len(pairs) / (ms / 1e3),
+                                             "butterflies_per_s": bfly / (ms / 1e3)}
+        plan.destroy()
+    orc = oracle.Oracle()
+    rr = random.Random(7)
+    got = [o.cpu().numpy().view(np.uint64) for o in outs]
+    for i in rr.sample(range(len(pairs)), 64):
+        a, b = pairs[i]
+        k = rr.randrange(got[i].size)
+        assert int(got[i][k]) == orc.product_coeff(a, b, k), "polymul result mismatch"
+    ctx.close()
+    return {"metric": "exact polynomial products/s (3 primes + CRT, one graph launch)", "unit": "products/s",
+            "value": res["lazy"]["products_per_s"],
+            "workload": "4096 pairs, n log-uniform 2^8..2^16, coefficients < 2^20", "sum_padded_len": words,
+            "butterflies_per_batch": bfly, "lazy": res["lazy"], "plain": res["plain"],
+            "lazy_over_plain": res["plain"]["ms_per_batch"] / res["lazy"]["ms_per_batch"]}
+
+
+def serving(args):
+    from .serve import PolymulServer, make_requests
+    ctx = hntt.Context(0)
+    budget = 8 << 30
+    # warm the twiddle tables of every length class, then find the saturation throughput
+    warm = make_requests(seed=50, count=40, rate_per_s=1e9)
+    PolymulServer(ctx, budget).run(warm)
+    sat_reqs = make_requests(seed=5, count=400, rate_per_s=1e9)  # everything arrives at once
+    sat = PolymulServer(ctx, budget).run(sat_reqs)
+    mu = sat["products_per_s"]
+    sweep = []
+    for frac in (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+        rate = frac * mu
+        count = int(min(400, max(60, rate * 1.5)))
+        reqs = make_requests(seed=5, count=count, rate_per_s=rate)
+        st = PolymulServer(ctx, budget).run(reqs)
+        st.update({"offered_fraction": frac, "offered_rate": rate})
+        sweep.append(st)
+    # spot-check results of the last run
+    import oracle
+    orc = oracle.Oracle()
+    for r in reqs[:: max(1, len(reqs) // 10)]:
+        k = random.Random(r.rid).randrange(r.nout)
+        assert int(r.result[k]) == orc.product_coeff(r.a, r.b, k)
+    ctx.close()
+    return {"metric": "serving: products/s at saturation, p50/p99 latency vs offered rate", "unit": "products/s",
+            "value": mu, "workload": "Poisson stream, n log-uniform 2^10..2^20, 3 primes + CRT, budget 8 GiB",
+            "saturation": sat, "sweep": sweep}
