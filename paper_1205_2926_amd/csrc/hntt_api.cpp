@@ -273,22 +273,35 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const
     if ((rc = table(powmod(omega_inv, C, p), r, &t.inv))) return rc;
     if ((rc = table(powmod(omega, R, p), c, &t.row_fwd))) return rc;
     if ((rc = table(powmod(omega_inv, R, p), c, &t.row_inv))) return rc;
-    // split twiddles, laid out like the data: entry (pos, col) = omega^(col * rev_r(pos)),
-    // and for the inverse L^-1 * omega^(-col * rev_r(pos)); interleaved with their W'
-    std::vector<uint64_t> f(2 * L), iv(2 * L);
-    for (uint64_t pos = 0; pos < R; ++pos) {
-      const uint64_t s = bitrev((unsigned)pos, r);
-      const uint64_t step_f = powmod(omega, s, p), step_i = powmod(omega_inv, s, p);
-      uint64_t xf = 1, xi = linv;
-      for (uint64_t col = 0; col < C; ++col) {
-        const uint64_t idx = 2 * (pos * C + col);
-        f[idx] = xf;
-        f[idx + 1] = shoup_constant(xf, p, bits);
-        iv[idx] = xi;
-        iv[idx + 1] = shoup_constant(xi, p, bits);
-        xf = mulmod(xf, step_f, p);
-        xi = mulmod(xi, step_i, p);
-      }
+    // Split twiddles as two factors per sub-transform (see Edge in ntt_pass.hip).
+    // Forward, applied on load in the row pass: row B (s = rev_r(B)) needs
+    // omega^(s pos) = omega^(s lo) * omega^(s hi 2^sf) with pos = hi 2^sf + lo, where
+    // sf = c - KH(c) is the boundary of the row pass's first register round.
+    // Inverse, applied on load in the column pass: column col needs
+    // L^-1 omega^(-col rev_r(pos)) with rev_r(pos) = rev_si(lo) 2^(r-si) + rev_(r-si)(hi),
+    // si = KL(r).  Each sub-transform's table is [lo factors | hi factors].
+    const RoundSplit rs_c = pass_split(c, bits), rs_r = pass_split(r, bits);
+    const int sf = c - rs_c.kh, si = rs_r.kl;
+    const uint64_t Sf = (1ull << sf) + (1ull << (c - sf)), Si = (1ull << si) + (1ull << (r - si));
+    std::vector<uint64_t> f(2 * R * Sf), iv(2 * C * Si);
+    auto put = [&](std::vector<uint64_t> &v, uint64_t idx, uint64_t w) {
+      v[2 * idx] = w;
+      v[2 * idx + 1] = shoup_constant(w, p, bits);
+    };
+    for (uint64_t B = 0; B < R; ++B) {
+      const uint64_t ws = powmod(omega, bitrev((unsigned)B, r), p);  // omega^s
+      const uint64_t wsh = powmod(ws, 1ull << sf, p);                 // omega^(s 2^sf)
+      uint64_t x = 1;
+      for (uint64_t lo = 0; lo < (1ull << sf); ++lo, x = mulmod(x, ws, p)) put(f, B * Sf + lo, x);
+      x = 1;
+      for (uint64_t hi = 0; hi < (1ull << (c - sf)); ++hi, x = mulmod(x, wsh, p)) put(f, B * Sf + (1ull << sf) + hi, x);
+    }
+    for (uint64_t col = 0; col < C; ++col) {
+      const uint64_t wc = powmod(omega_inv, col, p);  // omega^(-col)
+      for (uint64_t lo = 0; lo < (1ull << si); ++lo)
+        put(iv, col * Si + lo, powmod(wc, (uint64_t)bitrev((unsigned)lo, si) << (r - si), p));
+      for (uint64_t hi = 0; hi < (1ull << (r - si)); ++hi)
+        put(iv, col * Si + (1ull << si) + hi, mulmod(linv, powmod(wc, bitrev((unsigned)hi, r - si), p), p));
     }
     if ((rc = upload(ctx, f, bits, &t.tt_fwd))) return rc;
     if ((rc = upload(ctx, iv, bits, &t.tt_inv))) return rc;
@@ -368,12 +381,13 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const Plan &plan, const std::v
     cols.log_other = plan.c;
     cols.group = plan.g_cols;
     cols.tw = inverse ? t.inv : t.fwd;
-    cols.tt = inverse ? t.tt_inv : t.tt_fwd;
+    cols.tt = inverse ? t.tt_inv : nullptr;  // the split twiddle enters with the second pass
     rows.kind = PassKind::kRows;
     rows.n = plan.c;
     rows.log_other = plan.r;
     rows.group = plan.g_rows;
     rows.tw = inverse ? t.row_inv : t.row_fwd;
+    rows.tt = inverse ? nullptr : t.tt_fwd;
     if (!inverse) {
       cols.normalize = false;
       rows.normalize = norm;

@@ -165,28 +165,34 @@ struct KernelArgs {
   SlotParams slots[kMaxSlots];
 };
 
-// What happens to a word on its way in from HBM and out to HBM.
-template <bool Lazy, bool Cols>
+// What happens to a word on its way in from HBM and out to HBM.  The split
+// twiddle of a two-pass transform is applied where the data enters the second
+// pass: on load in the row pass (forward: omega^(s pos) for row s's position
+// pos) and on load in the column pass (inverse: L^-1 conj(omega)^(col rev(pos))).
+// It is the product of two factors, one indexed by the low SIGMA bits of the
+// position and one by the remaining high bits, read from a per-sub-transform
+// table [low factors (2^SIGMA pairs) | high factors (2^(n-SIGMA) pairs)] that is
+// small enough to stay in the L1/L2 caches.  SIGMA is the bit boundary of the
+// pass's first register round, so one factor is fixed per thread group and the
+// other is shared by all lanes of a sub-transform.  TT = false: no split twiddle.
+template <bool Lazy, bool Cols, bool TT, int N_LOG, int SIGMA>
 struct Edge {
   T p;
   int normalize, scale;
   T sw, swp;
-  const HNTT_GLOBAL Tw2 *__restrict__ tt;  // split twiddles of this thread's column (cols), stride C
-  size_t C;
+  const HNTT_GLOBAL Tw2 *__restrict__ tt;  // this sub-transform's factor table
   __device__ __forceinline__ T in(T x, int pos) const {
-    if constexpr (Cols && kInverse) {  // conj(omega)^(col s) L^-1 before the column transform
-      const Tw2 f = tt[(size_t)pos * C];
-      x = shoup_lazy<Wd>(x, f.x, f.y, p);
+    if constexpr (TT) {
+      const Tw2 hi = tt[(1 << SIGMA) + (pos >> SIGMA)];
+      const Tw2 lo = tt[pos & ((1 << SIGMA) - 1)];
+      x = shoup_lazy<Wd>(x, hi.x, hi.y, p);  // any input < beta -> [0,2p)
+      x = shoup_lazy<Wd>(x, lo.x, lo.y, p);
       if constexpr (!Lazy) x = csub<T>(x, p);
     }
     return x;
   }
   __device__ __forceinline__ T out(T x, int pos) const {
-    if constexpr (Cols && !kInverse) {  // omega^(col s) after the column transform
-      const Tw2 f = tt[(size_t)pos * C];
-      x = shoup_lazy<Wd>(x, f.x, f.y, p);
-      if constexpr (!Lazy) x = csub<T>(x, p);
-    } else if constexpr (!Cols && kInverse) {
+    if constexpr (!Cols && kInverse) {
       if (scale) {  // whole inverse transform: times L^-1, then reduced
         x = shoup_lazy<Wd>(x, sw, swp, p);
         if (normalize) x = csub<T>(x, p);
@@ -201,12 +207,12 @@ struct Edge {
 };
 
 // HBM side: position pos of this thread's sub-transform at gsub[pos * stride].
-template <bool Lazy, bool Cols>
+template <bool Lazy, bool Cols, class EdgeT>
 struct GlobalIO {
   static constexpr bool kContig = !Cols;
   HNTT_GLOBAL T *gsub;
   size_t stride;
-  Edge<Lazy, Cols> edge;
+  EdgeT edge;
   __device__ __forceinline__ T load(int pos) const { return edge.in(gsub[(size_t)pos * stride], pos); }
   __device__ __forceinline__ void store(int pos, T x) const { gsub[(size_t)pos * stride] = edge.out(x, pos); }
   // kContig only: kVec consecutive positions, pos a multiple of kVec
@@ -261,9 +267,11 @@ constexpr int padded_len(int N) {
   return Cols ? N + N / 32 : N + (N >= 32 ? N / 8 : 0);
 }
 
-template <bool Lazy, bool Cols, int KH, int KM, int KL>
+template <bool Lazy, bool Cols, int KH, int KM, int KL, bool TT>
 __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   constexpr int N_LOG = KH + KM + KL;
+  // bit boundary of the first register round (split-twiddle factorisation)
+  constexpr int SIGMA = kInverse ? KL : (KM + KL);
   constexpr int N = 1 << N_LOG;
   constexpr int KMAX = KH > KL ? (KH > KM ? KH : KM) : (KL > KM ? KL : KM);
   constexpr int TPT = 1 << (N_LOG - KMAX);
@@ -316,16 +324,20 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     const HNTT_GLOBAL Tw2 *__restrict__ twg = (const HNTT_GLOBAL Tw2 *)(sp.tw);
 
     HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(ptr);
-    Edge<Lazy, Cols> edge{p, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, nullptr, C};
-    GlobalIO<Lazy, Cols> gio;
+    using EdgeT = Edge<Lazy, Cols, TT, N_LOG, SIGMA>;
+    EdgeT edge{p, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, nullptr};
+    GlobalIO<Lazy, Cols, EdgeT> gio;
+    constexpr int kTTStride = (1 << SIGMA) + (1 << (N_LOG - SIGMA));
     if constexpr (Cols) {
       const size_t col = (size_t)unit * G + g;
       gio.gsub = gbase + col;
       gio.stride = C;
-      edge.tt = (const HNTT_GLOBAL Tw2 *)(sp.tt) + col;
+      if constexpr (TT) edge.tt = (const HNTT_GLOBAL Tw2 *)(sp.tt) + col * kTTStride;
     } else {
-      gio.gsub = gbase + ((size_t)unit * G + g) * N;
+      const size_t row = (size_t)unit * G + g;
+      gio.gsub = gbase + row * N;
       gio.stride = 1;
+      if constexpr (TT) edge.tt = (const HNTT_GLOBAL Tw2 *)(sp.tt) + row * kTTStride;
     }
     gio.edge = edge;
 
@@ -357,23 +369,36 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   }
 }
 
-template <bool Lazy, bool Cols, int KH, int KM, int KL>
+template <bool Lazy, bool Cols, int KH, int KM, int KL, bool TT>
 hipError_t launch_k(const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<Lazy, Cols, KH, KM, KL>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<Lazy, Cols, KH, KM, KL, TT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL((k_pass<Lazy, Cols, KH, KM, KL>), dim3(blocks), dim3(threads), lds, stream, a);
+  hipLaunchKernelGGL((k_pass<Lazy, Cols, KH, KM, KL, TT>), dim3(blocks), dim3(threads), lds, stream, a);
   return hipGetLastError();
+}
+
+// The split twiddle exists only in the second pass of a transform: the inverse
+// column pass and the forward row pass of a split transform.
+template <bool Lazy, bool Cols, int KH, int KM, int KL>
+hipError_t launch_tt(bool tt, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t stream) {
+  if constexpr (Cols != kInverse) {
+    (void)tt;
+    return launch_k<Lazy, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
+  } else {
+    return tt ? launch_k<Lazy, Cols, KH, KM, KL, true>(a, blocks, threads, lds, stream)
+              : launch_k<Lazy, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
+  }
 }
 
 // Round splits per word size; must agree with pass_split().
 template <bool Lazy, bool Cols>
-hipError_t dispatch_n(int n, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t s) {
+hipError_t dispatch_n(int n, bool tt, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t s) {
 #define HNTT_CASE(N, KH, KM, KL) \
-  case N: return launch_k<Lazy, Cols, KH, KM, KL>(a, blocks, threads, lds, s);
+  case N: return launch_tt<Lazy, Cols, KH, KM, KL>(tt, a, blocks, threads, lds, s);
   switch (n) {
     HNTT_CASE(1, 0, 0, 1)
     HNTT_CASE(2, 0, 0, 2)
@@ -445,10 +470,11 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   }
   const int blocks = (int)total;
   using namespace HNTT_NS;
-  if (pp.lazy) return cols ? dispatch_n<true, true>(n, a, blocks, threads, lds, stream)
-                           : dispatch_n<true, false>(n, a, blocks, threads, lds, stream);
-  return cols ? dispatch_n<false, true>(n, a, blocks, threads, lds, stream)
-              : dispatch_n<false, false>(n, a, blocks, threads, lds, stream);
+  const bool tt = pp.table ? pp.slots[0].tt != nullptr : pp.tt != nullptr;
+  if (pp.lazy) return cols ? dispatch_n<true, true>(n, tt, a, blocks, threads, lds, stream)
+                           : dispatch_n<true, false>(n, tt, a, blocks, threads, lds, stream);
+  return cols ? dispatch_n<false, true>(n, tt, a, blocks, threads, lds, stream)
+              : dispatch_n<false, false>(n, tt, a, blocks, threads, lds, stream);
 }
 
 }  // namespace hntt

@@ -149,11 +149,15 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t 
       sp.scale_w = t.linv;
       sp.scale_wp = t.linv_p;
       sp.tt = nullptr;
+      // the split twiddle enters with the second pass: rows (forward), columns (inverse)
       if (which == 0) sp.tw = inverse ? t.inv : t.fwd;               // whole
       else if (which == 1) {                                          // columns
         sp.tw = inverse ? t.inv : t.fwd;
-        sp.tt = inverse ? t.tt_inv : t.tt_fwd;
-      } else sp.tw = inverse ? t.row_inv : t.row_fwd;                 // rows
+        sp.tt = inverse ? t.tt_inv : nullptr;
+      } else {                                                        // rows
+        sp.tw = inverse ? t.row_inv : t.row_fwd;
+        sp.tt = inverse ? nullptr : t.tt_fwd;
+      }
     }
   };
   hipError_t e;
