@@ -279,7 +279,7 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const
     // sf = c - KH(c) is the boundary of the row pass's first register round.
     // Inverse, applied on load in the column pass: column col needs
     // L^-1 omega^(-col rev_r(pos)) with rev_r(pos) = rev_si(lo) 2^(r-si) + rev_(r-si)(hi),
-    // si = KL(r).  Each sub-transform's table is [lo factors | hi factors].
+    // si = KL(r).  Each sub-transform's factors are [lo factors | hi factors].
     const RoundSplit rs_c = pass_split(c, bits), rs_r = pass_split(r, bits);
     const int sf = c - rs_c.kh, si = rs_r.kl;
     const uint64_t Sf = (1ull << sf) + (1ull << (c - sf)), Si = (1ull << si) + (1ull << (r - si));
@@ -296,12 +296,14 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const
       x = 1;
       for (uint64_t hi = 0; hi < (1ull << (c - sf)); ++hi, x = mulmod(x, wsh, p)) put(f, B * Sf + (1ull << sf) + hi, x);
     }
+    // (the inverse table is factor-major, [factor][column], so that the adjacent
+    // columns of a workgroup read adjacent entries)
     for (uint64_t col = 0; col < C; ++col) {
       const uint64_t wc = powmod(omega_inv, col, p);  // omega^(-col)
       for (uint64_t lo = 0; lo < (1ull << si); ++lo)
-        put(iv, col * Si + lo, powmod(wc, (uint64_t)bitrev((unsigned)lo, si) << (r - si), p));
+        put(iv, lo * C + col, powmod(wc, (uint64_t)bitrev((unsigned)lo, si) << (r - si), p));
       for (uint64_t hi = 0; hi < (1ull << (r - si)); ++hi)
-        put(iv, col * Si + (1ull << si) + hi, mulmod(linv, powmod(wc, bitrev((unsigned)hi, r - si), p), p));
+        put(iv, ((1ull << si) + hi) * C + col, mulmod(linv, powmod(wc, bitrev((unsigned)hi, r - si), p), p));
     }
     if ((rc = upload(ctx, f, bits, &t.tt_fwd))) return rc;
     if ((rc = upload(ctx, iv, bits, &t.tt_inv))) return rc;

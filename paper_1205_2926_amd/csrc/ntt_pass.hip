@@ -61,6 +61,55 @@ typedef T Tw2 __attribute__((ext_vector_type(2)));
 // 16 bytes moved by one vector memory instruction.
 typedef uint32_t Vec16 __attribute__((ext_vector_type(4)));
 
+// Raw buffer accesses: 32-bit per-lane byte offset + uniform byte offset on a
+// buffer resource (base, size); accesses beyond the size read 0 / are dropped.
+constexpr int kBufferFlags = 0x00020000;  // gfx9 family raw-buffer descriptor word 3
+// A workgroup-uniform 64-bit value, marked uniform for the compiler (it must be
+// uniform already: this reads lane 0's copy).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
+}
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+  } else {
+    typedef int V2 __attribute__((ext_vector_type(2)));
+    const V2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    return (T)(uint32_t)v.x | ((T)(uint32_t)v.y << 32);
+  }
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T x) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32((int)x, r, (int)voff, (int)soff, 0);
+  } else {
+    typedef int V2 __attribute__((ext_vector_type(2)));
+    V2 v;
+    v.x = (int)(uint32_t)x;
+    v.y = (int)(uint32_t)(x >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, 0);
+  }
+}
+__device__ __forceinline__ Tw2 buf_load_tw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  Tw2 w;
+  if constexpr (sizeof(T) == 4) {
+    typedef int V2 __attribute__((ext_vector_type(2)));
+    const V2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    w.x = (T)(uint32_t)v.x;
+    w.y = (T)(uint32_t)v.y;
+  } else {
+    typedef int V4 __attribute__((ext_vector_type(4)));
+    const V4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    w.x = (T)(uint32_t)v.x | ((T)(uint32_t)v.y << 32);
+    w.y = (T)(uint32_t)v.z | ((T)(uint32_t)v.w << 32);
+  }
+  return w;
+}
+
 template <bool Lazy>
 __device__ __forceinline__ void bfly(T &x, T &y, T w, T wp, T p, T p2) {
   if constexpr (kInverse) {
@@ -93,7 +142,8 @@ constexpr int kVec = 16 / sizeof(T);
 // LowRound: b_lo = 0, the twiddle indices are compile-time constants and are
 // read from global memory with scalar loads; the butterflies with twiddle 1
 // skip the product.  Otherwise the twiddles come from the LDS copy `tws`.
-// Src/Dst provide load/store of one position, and of kVec consecutive
+// Src/Dst provide load2/store2 of one position given as a per-lane part plus a
+// uniform part with disjoint bits, and load_vec/store_vec of kVec consecutive
 // positions when their kContig flag is set.
 template <bool Lazy, int N_LOG, int K, bool LowRound, class Src, class Dst>
 __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws, const HNTT_GLOBAL Tw2 *__restrict__ twg, T p,
@@ -110,7 +160,7 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws
       for (int e = 0; e < M; e += kVec) src.load_vec(base + e, &v[e]);
     } else {
 #pragma unroll
-      for (int e = 0; e < M; ++e) v[e] = src.load(base | (e << b_lo));
+      for (int e = 0; e < M; ++e) v[e] = src.load2(base, e << b_lo);
     }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
@@ -139,7 +189,7 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws
       for (int e = 0; e < M; e += kVec) dst.store_vec(base + e, &v[e]);
     } else {
 #pragma unroll
-      for (int e = 0; e < M; ++e) dst.store(base | (e << b_lo), v[e]);
+      for (int e = 0; e < M; ++e) dst.store2(base, e << b_lo, v[e]);
     }
   }
 }
@@ -180,17 +230,23 @@ struct Edge {
   T p;
   int normalize, scale;
   T sw, swp;
-  const HNTT_GLOBAL Tw2 *__restrict__ tt;  // this sub-transform's factor table
-  __device__ __forceinline__ T in(T x, int pos) const {
+  __amdgpu_buffer_rsrc_t tt;  // factor tables of the pass
+  uint32_t tt_off;            // byte offset of this sub-transform's first factor
+  uint32_t tt_step;           // bytes between consecutive factors of one sub-transform
+  // pos = lp + up with disjoint bits: lp varies per lane, up is uniform
+  __device__ __forceinline__ T in(T x, int lp, int up) const {
     if constexpr (TT) {
-      const Tw2 hi = tt[(1 << SIGMA) + (pos >> SIGMA)];
-      const Tw2 lo = tt[pos & ((1 << SIGMA) - 1)];
+      constexpr int kMask = (1 << SIGMA) - 1;
+      const Tw2 hi = buf_load_tw(tt, tt_off + (uint32_t)((1 << SIGMA) + (lp >> SIGMA)) * tt_step,
+                                 (uint32_t)(up >> SIGMA) * tt_step);
+      const Tw2 lo = buf_load_tw(tt, tt_off + (uint32_t)(lp & kMask) * tt_step, (uint32_t)(up & kMask) * tt_step);
       x = shoup_lazy<Wd>(x, hi.x, hi.y, p);  // any input < beta -> [0,2p)
       x = shoup_lazy<Wd>(x, lo.x, lo.y, p);
       if constexpr (!Lazy) x = csub<T>(x, p);
     }
     return x;
   }
+  __device__ __forceinline__ T in(T x, int pos) const { return in(x, pos, 0); }
   __device__ __forceinline__ T out(T x, int pos) const {
     if constexpr (!Cols && kInverse) {
       if (scale) {  // whole inverse transform: times L^-1, then reduced
@@ -206,18 +262,39 @@ struct Edge {
   }
 };
 
-// HBM side: position pos of this thread's sub-transform at gsub[pos * stride].
+// HBM side: position pos of this thread's sub-transform is word off + pos*stride
+// of the transform at `base`.  The base is uniform across the workgroup (scalar
+// registers) and the offset is 32-bit, so accesses use the scalar-base addressing
+// form instead of per-lane 64-bit address arithmetic.
 template <bool Lazy, bool Cols, class EdgeT>
 struct GlobalIO {
   static constexpr bool kContig = !Cols;
-  HNTT_GLOBAL T *gsub;
-  size_t stride;
+  HNTT_GLOBAL T *base;
+  __amdgpu_buffer_rsrc_t rsrc;  // Cols: the transform as a buffer
+  uint32_t off;
+  uint32_t stride;
   EdgeT edge;
-  __device__ __forceinline__ T load(int pos) const { return edge.in(gsub[(size_t)pos * stride], pos); }
-  __device__ __forceinline__ void store(int pos, T x) const { gsub[(size_t)pos * stride] = edge.out(x, pos); }
+  __device__ __forceinline__ T load2(int lp, int up) const {
+    if constexpr (Cols) {
+      const T x = buf_load(rsrc, (off + (uint32_t)lp * stride) * (uint32_t)sizeof(T),
+                           (uint32_t)up * stride * (uint32_t)sizeof(T));
+      return edge.in(x, lp, up);
+    } else {
+      return edge.in(base[off + (uint32_t)(lp + up)], lp, up);
+    }
+  }
+  __device__ __forceinline__ void store2(int lp, int up, T x) const {
+    x = edge.out(x, lp + up);
+    if constexpr (Cols) {
+      buf_store(rsrc, (off + (uint32_t)lp * stride) * (uint32_t)sizeof(T), (uint32_t)up * stride * (uint32_t)sizeof(T),
+                x);
+    } else {
+      base[off + (uint32_t)(lp + up)] = x;
+    }
+  }
   // kContig only: kVec consecutive positions, pos a multiple of kVec
   __device__ __forceinline__ void load_vec(int pos, T *v) const {
-    const Vec16 q = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(gsub + pos);
+    const Vec16 q = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(base + (off + (uint32_t)pos));
     const T *w = reinterpret_cast<const T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) v[i] = edge.in(w[i], pos + i);
@@ -227,7 +304,7 @@ struct GlobalIO {
     T *w = reinterpret_cast<T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) w[i] = edge.out(v[i], pos + i);
-    *reinterpret_cast<HNTT_GLOBAL Vec16 *>(gsub + pos) = q;
+    *reinterpret_cast<HNTT_GLOBAL Vec16 *>(base + (off + (uint32_t)pos)) = q;
   }
 };
 
@@ -244,8 +321,8 @@ struct LdsIO {
     if constexpr (Cols) return (pos + (pos >> 5)) * G + g;
     else return g * pitch + pos + ((pos >> 5) << 2);
   }
-  __device__ __forceinline__ T load(int pos) const { return tile[idx(pos)]; }
-  __device__ __forceinline__ void store(int pos, T x) const { tile[idx(pos)] = x; }
+  __device__ __forceinline__ T load2(int lp, int up) const { return tile[idx(lp + up)]; }
+  __device__ __forceinline__ void store2(int lp, int up, T x) const { tile[idx(lp + up)] = x; }
   __device__ __forceinline__ void load_vec(int pos, T *v) const {
     const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + idx(pos));
     const T *w = reinterpret_cast<const T *>(&q);
@@ -323,21 +400,30 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     const T p = (T)sp.p, p2 = p + p;
     const HNTT_GLOBAL Tw2 *__restrict__ twg = (const HNTT_GLOBAL Tw2 *)(sp.tw);
 
-    HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(ptr);
+    HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(uniform64(ptr));
     using EdgeT = Edge<Lazy, Cols, TT, N_LOG, SIGMA>;
-    EdgeT edge{p, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, nullptr};
+    EdgeT edge{p, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, make_rsrc(sp.tt, 0), 0, 0};
     GlobalIO<Lazy, Cols, EdgeT> gio;
-    constexpr int kTTStride = (1 << SIGMA) + (1 << (N_LOG - SIGMA));
+    constexpr uint32_t kTTStride = (1u << SIGMA) + (1u << (N_LOG - SIGMA));
+    const uint32_t nsub = Cols ? (uint32_t)C : (1u << a.log_other);  // sub-transforms per transform
+    if constexpr (TT)
+      edge.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt), nsub * kTTStride * (uint32_t)sizeof(Tw2));
+    gio.base = gbase;
     if constexpr (Cols) {
-      const size_t col = (size_t)unit * G + g;
-      gio.gsub = gbase + col;
-      gio.stride = C;
-      if constexpr (TT) edge.tt = (const HNTT_GLOBAL Tw2 *)(sp.tt) + col * kTTStride;
+      const uint32_t col = (uint32_t)unit * G + g;
+      gio.rsrc = make_rsrc((const void *)gbase, (uint32_t)(C * N * sizeof(T)));
+      gio.off = col;
+      gio.stride = (uint32_t)C;
+      // factor-major table [factor][column]: adjacent columns' factors are adjacent
+      edge.tt_off = col * (uint32_t)sizeof(Tw2);
+      edge.tt_step = (uint32_t)C * (uint32_t)sizeof(Tw2);
     } else {
-      const size_t row = (size_t)unit * G + g;
-      gio.gsub = gbase + row * N;
+      const uint32_t row = (uint32_t)unit * G + g;
+      gio.off = row * N;
       gio.stride = 1;
-      if constexpr (TT) edge.tt = (const HNTT_GLOBAL Tw2 *)(sp.tt) + row * kTTStride;
+      // row-major table [row][factor]: a row's lanes read consecutive low factors
+      edge.tt_off = row * kTTStride * (uint32_t)sizeof(Tw2);
+      edge.tt_step = (uint32_t)sizeof(Tw2);
     }
     gio.edge = edge;
 
@@ -355,7 +441,28 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
           __syncthreads();
         }
-        round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, gio);
+        if constexpr (Cols) {
+          round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, gio);
+        } else {
+          // Rows: a thread's low-round outputs are 2^KL consecutive words, so direct
+          // stores would put neighbouring lanes 2^KL words apart.  Stage them in LDS
+          // and write the tile out with consecutive lanes on consecutive 16 bytes.
+          round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, lio);
+          __syncthreads();
+          constexpr int kPitch = padded_len<false>(N);
+          constexpr int kChunks = N / kVec;
+          HNTT_GLOBAL T *const rows0 = gbase + (size_t)unit * G * N;
+          for (int i = threadIdx.x; i < G * kChunks; i += blockDim.x) {
+            const int row = i / kChunks, c = (i % kChunks) * kVec;
+            const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2));
+            Vec16 o;
+            const T *w = reinterpret_cast<const T *>(&q);
+            T *wo = reinterpret_cast<T *>(&o);
+#pragma unroll
+            for (int j = 0; j < kVec; ++j) wo[j] = edge.out(w[j], c + j);
+            *reinterpret_cast<HNTT_GLOBAL Vec16 *>(rows0 + (size_t)row * N + c) = o;
+          }
+        }
       } else {
         round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, gio, lio);
         __syncthreads();  // tile and twiddle table complete
