@@ -4,8 +4,8 @@ For a (length, word size, batch) shape it times forward+inverse transforms on
 the GPU under every legal schedule in a small search space (columns per
 workgroup in the column pass, rows per workgroup in the row pass, transforms
 per chunk) and installs the fastest one on the context with
-``Context.set_tuning``.  Results are cached in a JSON file keyed by GPU name
-and shape (``$HNTT_TUNE_CACHE``, default ``~/.cache/hntt/tune.json``).  The
+``Context.set_tuning``.  Results are cached in a JSON file keyed by the GPU's compute-unit
+count, memory size and the shape (``$HNTT_TUNE_CACHE``, default ``~/.cache/hntt/tune.json``).  The
 schedule never changes results, only speed.
 
 CLI: ``python -m paper_1205_2926_amd.autotune --log2-len 20 --batch 64``
@@ -27,8 +27,14 @@ SPACE = {"g_cols": [4, 8, 16], "g_rows": [1, 2, 4, 8, 16], "batch_chunk": [8, 16
 
 
 def _key(log2_len, word_bits, batch, plain):
-    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-    return f"{name}|l={log2_len}|w={word_bits}|b={batch}|{'plain' if plain else 'lazy'}"
+    # the device is identified by its compute-unit count and memory size: the marketing name is
+    # not reported reliably (profilers that intercept the runtime can leave it empty)
+    if torch.cuda.is_available():
+        props = torch.cuda.get_device_properties(0)
+        dev = f"cu{props.multi_processor_count}|mem{props.total_memory >> 30}G"
+    else:
+        dev = "cpu"
+    return f"{dev}|l={log2_len}|w={word_bits}|b={batch}|{'plain' if plain else 'lazy'}"
 
 
 def load_cache(path: str = CACHE) -> dict:
