@@ -204,3 +204,17 @@ def test_serving_arena_allocator():
     a.release(0, 1024)
     a.release(y, 1000)
     assert a.free == [(0, 4096)] and a.used == 0 and a.peak == 2048
+
+
+def test_serving_workspace_bound_covers_library_size():
+    """The server's additive per-request workspace bound is never below the library's exact
+    workspace size of a group (host-only sizing, no GPU)."""
+    import numpy as np
+    from paper_1205_2926_amd.serve import Request, _GROUP_SLACK
+    gen = np.random.default_rng(0)
+    for _ in range(100):
+        k = int(gen.integers(1, 70))
+        reqs = [Request(i, 0.0, np.zeros(int(2 ** gen.uniform(0, 20)), np.uint32),
+                        np.zeros(int(2 ** gen.uniform(0, 20)), np.uint32)) for i in range(k)]
+        exact = hntt.polymul_workspace_size([(r.a.size, r.b.size) for r in reqs])
+        assert exact <= sum(r.workspace_bound() for r in reqs) + _GROUP_SLACK
