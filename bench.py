@@ -5,13 +5,13 @@ Workload: 64 forward + inverse NTTs of length 2^20 over p = 998244353 on 32-bit
 words (omega = 3^((p-1)/2^20)), uniform residues from seed 2, already resident
 in HBM.  One step = the forward transform of the whole batch followed by the
 inverse (so every step starts from the same data).  The same steps are timed
-again with the fully reducing (plain) butterflies under the identical kernel
-schedule.
+again with the fully reducing (plain) butterflies of Algorithm 2 and with the
+Montgomery butterflies of Algorithm 5 under the same kernel template.
 
 Reported: butterflies/s (batch * l * L/2 per direction, counted as the paper
 does), the roofline of the dominant kernel (HIP-event durations of the launches
-inside the timed region), the compulsory-byte HBM fraction, the lazy/plain
-ratio, and the CPU oracle timed on a bounded sample on the host cores.
+inside the timed region), the compulsory-byte HBM fraction, the lazy/plain and
+lazy/Montgomery ratios, and the CPU oracle timed on a bounded sample on the host cores.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -44,6 +44,7 @@ def parse():
                     help="transforms (forward + inverse, length 2^20) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-mont", action="store_true", help="skip the Montgomery-butterfly (Algorithm 5) comparison")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in schedule instead of the autotuner's")
     ap.add_argument("--workload", default="batch64",
                     choices=["batch64", "single1k", "u64", "polymul", "serving"],
@@ -71,19 +72,20 @@ def pass_butterflies(name: str, batch: int, l: int) -> int:
     return batch * n * ((1 << l) // 2)
 
 
-def time_steps(ctx, x, p, w, plain, steps, warmup):
+def time_steps(ctx, x, p, w, policy, steps, warmup):
     import torch
+    kw = {"plain": policy == "plain", "mont": policy == "mont"}
     for _ in range(warmup):
-        ctx.ntt_forward(x, p, w, plain=plain)
-        ctx.ntt_inverse(x, p, w, plain=plain)
+        ctx.ntt_forward(x, p, w, **kw)
+        ctx.ntt_inverse(x, p, w, **kw)
     torch.cuda.synchronize()
     ctx.trace_reset()
     ctx.trace(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.ntt_forward(x, p, w, plain=plain)
-        ctx.ntt_inverse(x, p, w, plain=plain)
+        ctx.ntt_forward(x, p, w, **kw)
+        ctx.ntt_inverse(x, p, w, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.trace(False)
@@ -173,13 +175,14 @@ def main():
     res = {}
     schedules = {}
     from paper_1205_2926_amd import autotune
-    for policy in (["lazy"] if args.no_plain else ["lazy", "plain"]):
+    policies = ["lazy"] + ([] if args.no_plain else ["plain"]) + ([] if args.no_mont else ["mont"])
+    for policy in policies:
         if args.no_tune:
             ctx.set_tuning(l, cfg.word_bits)
         else:  # each butterfly gets its own best schedule (cached per GPU and shape)
-            autotune.tune(ctx, x, p, w, plain=policy == "plain")
+            autotune.tune(ctx, x, p, w, policy=policy)
         schedules[policy] = ctx.get_plan(l, cfg.word_bits)
-        sec, kernels = time_steps(ctx, x, p, w, policy == "plain", args.steps, args.warmup)
+        sec, kernels = time_steps(ctx, x, p, w, policy, args.steps, args.warmup)
         res[policy] = (sec, kernels)
     assert np.array_equal(x.cpu().numpy().view(np.uint32), x_np), "data changed across steps"
 
@@ -220,11 +223,12 @@ def main():
         "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in kernels.items()},
         "schedule": schedules.get("lazy"),
     }
-    if "plain" in res:
-        psec, pk = res["plain"]
-        out["plain"] = {"value": bfly_step / psec, "ms_per_step": psec * 1e3, "schedule": schedules["plain"],
-                        "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in pk.items()}}
-        out["lazy_over_plain"] = psec / sec
+    for other in ("plain", "mont"):
+        if other in res:
+            psec, pk = res[other]
+            out[other] = {"value": bfly_step / psec, "ms_per_step": psec * 1e3, "schedule": schedules[other],
+                          "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in pk.items()}}
+            out[f"lazy_over_{other}"] = psec / sec
     if not args.no_cpu_baseline:
         cb, fwd, rows = cpu_baseline(cfg, w, x_np, args.cpu_sample)
         assert np.array_equal(fwd[0], fwd0.astype(np.uint64)), "GPU forward differs from the oracle"

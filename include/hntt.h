@@ -14,7 +14,10 @@
  * kept in [0,2p)) and Algorithm 4 (inverse, residues kept in [0,4p)), each
  * multiplying by a precomputed Shoup constant W' = floor(W beta / p).  The
  * flag HNTT_PLAIN selects the fully reducing butterfly of Algorithm 2 (and its
- * inverse counterpart) under the same kernel schedule, for comparison.
+ * inverse counterpart) under the same kernel schedule, for comparison; the
+ * flag HNTT_MONT selects the Montgomery butterfly of Algorithm 5 (and the
+ * inverse butterfly of Algorithm 4 with Montgomery's product), whose tables
+ * hold only W beta mod p per root.
  *
  * Conventions shared by every entry point
  *   - Return value: HNTT_OK (0) or a negative HNTT_E* status.  Nothing throws.
@@ -54,6 +57,9 @@ enum {
 #define HNTT_PLAIN 0x1u        /* fully reducing butterflies (Algorithm 2 and its DIT twin) */
 #define HNTT_NO_NORMALIZE 0x2u /* skip the final reduction: forward leaves [0,2p) (lazy),
                                   inverse leaves [0,4p) (lazy); for chained pipelines only */
+#define HNTT_MONT 0x8u         /* Montgomery butterflies: Algorithm 5 (Section 4) forward and
+                                  Algorithm 4 with Montgomery's product inverse; tables hold
+                                  one word W beta mod p per root; same ranges and bounds as lazy */
 
 typedef struct hntt_ctx hntt_ctx;
 
@@ -77,9 +83,9 @@ const char *hntt_last_error(const hntt_ctx *ctx);
 /* One transform: `data` is a device array of 2^log2_len words of word_bits
  * bits (32: uint32_t, 64: uint64_t), transformed in place, aligned to 16
  * bytes (or to its size, if that is smaller).
- *   p        prime, p = 1 (mod 2^log2_len).  Lazy butterflies need p < beta/4
- *            (Algorithm 3 input conditions); HNTT_PLAIN needs p < beta/2
- *            (Algorithm 2 input conditions); beta = 2^word_bits.
+ *   p        prime, p = 1 (mod 2^log2_len).  Lazy and Montgomery butterflies
+ *            need p < beta/4 (Algorithm 3 and 5 input conditions); HNTT_PLAIN
+ *            needs p < beta/2 (Algorithm 2 input conditions); beta = 2^word_bits.
  *   omega    a primitive 2^log2_len-th root of unity mod p (Section 1): the
  *            transform is defined by it, another root permutes the output.
  *   log2_len 1 <= l <= 30 (and 2^l words must be addressable).
@@ -97,8 +103,9 @@ typedef struct {
  * butterfly).  Natural-order input in [0,p), bit-reversed output in [0,p).
  * Descriptors may mix primes, lengths and word sizes; descriptors that share
  * (p, omega, log2_len, word_bits) are transformed by the same launches.
- * Two descriptors must not name overlapping data.  flags: HNTT_PLAIN,
- * HNTT_NO_NORMALIZE.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+ * Two descriptors must not name overlapping data.  flags: HNTT_PLAIN or
+ * HNTT_MONT (not both: EINVAL), HNTT_NO_NORMALIZE.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
 int hntt_ntt_forward(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream);
 
 /* Inverse NTT (Section 4: Algorithm 1 run backwards with the Algorithm 4
@@ -140,7 +147,8 @@ int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint3
  * operand preparation, pointwise products and CRT run as persistent kernels
  * over the whole batch.
  * flags: HNTT_PLAIN (fully reducing butterflies), HNTT_NO_GRAPH (enqueue the
- * kernels directly instead of replaying a recorded HIP graph).
+ * kernels directly instead of replaying a recorded HIP graph); HNTT_MONT is
+ * not accepted here (EINVAL).
  * Errors: EINVAL (NULL/misaligned pointer, empty operand), EUNSUPPORTED
  * (padded length above 2^23), ENOMEM, EDEVICE. */
 typedef struct {
@@ -249,12 +257,15 @@ int hntt_trace_read(hntt_ctx *ctx, char *buf, size_t *len);
 int hntt_trace_reset(hntt_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
- * Device unit test of the butterflies themselves (Algorithms 2, 3, 4).
+ * Device unit test of the butterflies themselves (Algorithms 2, 3, 4, 5).
  * kind: 0 = Algorithm 2 (plain forward), 1 = Algorithm 3 (lazy forward),
- *       2 = Algorithm 4 (lazy inverse),  3 = plain inverse (fully reducing).
- * For i < n: (xo[i], yo[i]) = butterfly(x[i], y[i]) with twiddle w[i] and its
- * Shoup constant computed on the host.  All arrays are device arrays of
- * word_bits-bit words.  Inputs must satisfy the algorithm's stated ranges.
+ *       2 = Algorithm 4 (lazy inverse),  3 = plain inverse (fully reducing),
+ *       4 = Algorithm 5 (Montgomery forward), 5 = Montgomery lazy inverse
+ *       (Algorithm 4 with the product of Algorithm 5).
+ * For i < n: (xo[i], yo[i]) = butterfly(x[i], y[i]).  Kinds 0-3: w[i] is the
+ * twiddle W and wprime[i] its Shoup constant floor(W beta / p); kinds 4-5: w[i]
+ * is W beta mod p and wprime[i] is p^-1 mod beta.  All arrays are device arrays
+ * of word_bits-bit words.  Inputs must satisfy the algorithm's stated ranges.
  * Errors: EINVAL, EUNSUPPORTED, EDEVICE.
  * ------------------------------------------------------------------------- */
 int hntt_debug_butterfly(hntt_ctx *ctx, int kind, uint32_t word_bits, uint64_t p, const void *x,

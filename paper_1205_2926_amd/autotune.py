@@ -26,7 +26,7 @@ CACHE = os.environ.get("HNTT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), 
 SPACE = {"g_cols": [4, 8, 16], "g_rows": [1, 2, 4, 8, 16], "batch_chunk": [8, 16, 32, 64]}
 
 
-def _key(log2_len, word_bits, batch, plain):
+def _key(log2_len, word_bits, batch, policy):
     # the device is identified by its compute-unit count and memory size: the marketing name is
     # not reported reliably (profilers that intercept the runtime can leave it empty)
     if torch.cuda.is_available():
@@ -34,7 +34,7 @@ def _key(log2_len, word_bits, batch, plain):
         dev = f"cu{props.multi_processor_count}|mem{props.total_memory >> 30}G"
     else:
         dev = "cpu"
-    return f"{dev}|l={log2_len}|w={word_bits}|b={batch}|{'plain' if plain else 'lazy'}"
+    return f"{dev}|l={log2_len}|w={word_bits}|b={batch}|{policy}"
 
 
 def load_cache(path: str = CACHE) -> dict:
@@ -53,15 +53,16 @@ def save_cache(cache: dict, path: str = CACHE):
     os.replace(tmp, path)
 
 
-def _time(ctx, x, p, w, plain, reps):
+def _time(ctx, x, p, w, policy, reps):
+    kw = {"plain": policy == "plain", "mont": policy == "mont"}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ctx.ntt_forward(x, p, w, plain=plain)
-    ctx.ntt_inverse(x, p, w, plain=plain)
+    ctx.ntt_forward(x, p, w, **kw)
+    ctx.ntt_inverse(x, p, w, **kw)
     torch.cuda.synchronize()
     ev0.record()
     for _ in range(reps):
-        ctx.ntt_forward(x, p, w, plain=plain)
-        ctx.ntt_inverse(x, p, w, plain=plain)
+        ctx.ntt_forward(x, p, w, **kw)
+        ctx.ntt_inverse(x, p, w, **kw)
     ev1.record()
     torch.cuda.synchronize()
     return ev0.elapsed_time(ev1) / reps
@@ -83,12 +84,14 @@ def candidates(ctx, log2_len, word_bits, batch):
 
 
 def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: int = 3, use_cache: bool = True,
-         verbose: bool = False) -> dict:
-    """Pick and install the fastest schedule for transforms shaped like x ([batch, 2^l])."""
+         verbose: bool = False, policy: str = None) -> dict:
+    """Pick and install the fastest schedule for transforms shaped like x ([batch, 2^l]) under a
+    butterfly policy ("lazy", "plain" or "mont"; `plain=True` is shorthand for "plain")."""
+    policy = policy or ("plain" if plain else "lazy")
     batch, L = x.shape
     log2_len = L.bit_length() - 1
     word_bits = x.element_size() * 8
-    key = _key(log2_len, word_bits, batch, plain)
+    key = _key(log2_len, word_bits, batch, policy)
     cache = load_cache() if use_cache else {}
     if key in cache:
         best = cache[key]["best"]
@@ -100,7 +103,7 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
     t0 = time.time()
     for cand in candidates(ctx, log2_len, word_bits, batch):
         ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
-        ms = _time(ctx, x, p, omega, plain, reps)
+        ms = _time(ctx, x, p, omega, policy, reps)
         trials.append({**cand, "ms": ms})
         if verbose:
             print(f"  {cand} -> {ms:.4f} ms", flush=True)
@@ -118,7 +121,7 @@ def main():
     ap.add_argument("--log2-len", type=int, default=20)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--word-bits", type=int, default=32)
-    ap.add_argument("--plain", action="store_true")
+    ap.add_argument("--policy", choices=("lazy", "plain", "mont"), default="lazy")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--no-cache", action="store_true")
     args = ap.parse_args()
@@ -130,7 +133,7 @@ def main():
     host = uniform_residues(99, (args.batch, 1 << args.log2_len), p, dt)
     x = torch.from_numpy(host.view(np.int32 if args.word_bits == 32 else np.int64)).cuda()
     ctx = hntt.Context(0)
-    rec = tune(ctx, x, p, w, plain=args.plain, reps=args.reps, use_cache=not args.no_cache, verbose=True)
+    rec = tune(ctx, x, p, w, policy=args.policy, reps=args.reps, use_cache=not args.no_cache, verbose=True)
     print(json.dumps(rec))
 
 

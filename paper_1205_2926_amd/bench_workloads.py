@@ -1,7 +1,7 @@
 """Measurements of the non-headline workloads for ``bench.py --workload ...``.
 
 single1k  one forward NTT of 1024 residues (latency, lazy and plain)
-u64       8 NTTs of length 2^22 over the 62-bit prime, forward + inverse, lazy vs plain
+u64       8 NTTs of length 2^22 over the 62-bit prime, forward + inverse, lazy vs plain vs Montgomery
 polymul   4096 products with log-uniform lengths 2^8..2^16, three primes + CRT, one graph launch
 serving   Poisson stream of products (lengths 2^10..2^20), rate swept up to saturation
 Each returns one JSON-able dict.  Inputs are the seeded synthetic workloads of
@@ -63,18 +63,19 @@ def u64(args):
     x_np = cfg.data()
     x = torch.from_numpy(x_np.view(np.int64)).cuda()
     res = {}
-    for plain in (False, True):
-        autotune.tune(ctx, x, p, w, plain=plain)
-        ms = _events_ms(lambda: (ctx.ntt_forward(x, p, w, plain=plain), ctx.ntt_inverse(x, p, w, plain=plain)),
-                        args.steps)
-        res["plain" if plain else "lazy"] = {"ms_per_step": ms, "butterflies_per_s": 2 * cfg.butterflies / (ms / 1e3),
-                                             "schedule": ctx.get_plan(l, 64)}
+    for policy in ("lazy", "plain", "mont"):
+        kw = {"plain": policy == "plain", "mont": policy == "mont"}
+        autotune.tune(ctx, x, p, w, policy=policy)
+        ms = _events_ms(lambda: (ctx.ntt_forward(x, p, w, **kw), ctx.ntt_inverse(x, p, w, **kw)), args.steps)
+        res[policy] = {"ms_per_step": ms, "butterflies_per_s": 2 * cfg.butterflies / (ms / 1e3),
+                       "schedule": ctx.get_plan(l, 64)}
     assert np.array_equal(x.cpu().numpy().view(np.uint64), x_np), "u64 round trip mismatch"
     ctx.close()
     return {"metric": "NTT butterflies/s, 64-bit words", "unit": "butterflies/s",
             "value": res["lazy"]["butterflies_per_s"], "workload": "8 x 2^22 forward+inverse, p=2^62-ish, u64",
-            "p": p, "lazy": res["lazy"], "plain": res["plain"],
-            "lazy_over_plain": res["plain"]["ms_per_step"] / res["lazy"]["ms_per_step"]}
+            "p": p, "lazy": res["lazy"], "plain": res["plain"], "mont": res["mont"],
+            "lazy_over_plain": res["plain"]["ms_per_step"] / res["lazy"]["ms_per_step"],
+            "lazy_over_mont": res["mont"]["ms_per_step"] / res["lazy"]["ms_per_step"]}
 
 
 def polymul(args):

@@ -195,11 +195,39 @@ Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits) {
   return pl;
 }
 
+// p^-1 mod 2^bits for odd p (Newton's iteration doubles the correct low bits).
+static uint64_t inv_mod_beta(uint64_t p, int bits) {
+  uint64_t x = p;  // p p = 1 mod 8
+  for (int i = 0; i < 5; ++i) x *= 2 - p * x;
+  return bits == 64 ? x : (x & 0xFFFFFFFFull);
+}
+
+// Table entries of one twiddle W: (W, floor(W beta / p)) in Shoup form, or the
+// single word W beta mod p in Montgomery form.
+struct TableForm {
+  uint64_t p;
+  int bits;
+  bool mont;
+  uint64_t beta_mod_p;
+  TableForm(uint64_t p_, int bits_, bool mont_) : p(p_), bits(bits_), mont(mont_) {
+    beta_mod_p = powmod(2 % p_, (uint64_t)bits_, p_);
+  }
+  size_t words() const { return mont ? 1 : 2; }
+  void put(std::vector<uint64_t> &v, size_t idx, uint64_t w) const {
+    if (mont) {
+      v[idx] = mulmod(w, beta_mod_p, p);
+    } else {
+      v[2 * idx] = w;
+      v[2 * idx + 1] = shoup_constant(w, p, bits);
+    }
+  }
+};
+
 // Per-stage ("heap") table for a transform of length N = 2^n with root w_N:
-// entry (1 << b) + k, b < n, k < 2^b, holds the pair (W, W') for
-// W = w_N^(k << (n-1-b)), the twiddle of the stage that pairs position bit b;
-// W' = floor(W beta / p).  Entry 0 is unused.  Stored as interleaved words.
-static void heap_table(uint64_t root, int n, uint64_t p, int bits, std::vector<uint64_t> &out) {
+// entry (1 << b) + k, b < n, k < 2^b, holds W = w_N^(k << (n-1-b)), the twiddle
+// of the stage that pairs position bit b, in the table form.  Entry 0 holds 1.
+static void heap_table(uint64_t root, int n, const TableForm &form, std::vector<uint64_t> &out) {
+  const uint64_t p = form.p;
   const size_t N = (size_t)1 << n;
   std::vector<uint64_t> pw(N / 2 > 0 ? N / 2 : 1);
   uint64_t x = 1;
@@ -207,15 +235,10 @@ static void heap_table(uint64_t root, int n, uint64_t p, int bits, std::vector<u
     pw[j] = x;
     x = mulmod(x, root, p);
   }
-  out.assign(2 * N, 0);
-  out[0] = 1;
-  out[1] = shoup_constant(1, p, bits);
+  out.assign(form.words() * N, 0);
+  form.put(out, 0, 1);
   for (int b = 0; b < n; ++b)
-    for (size_t k = 0; k < ((size_t)1 << b); ++k) {
-      const uint64_t w = pw[k << (n - 1 - b)];
-      out[2 * (((size_t)1 << b) + k)] = w;
-      out[2 * (((size_t)1 << b) + k) + 1] = shoup_constant(w, p, bits);
-    }
+    for (size_t k = 0; k < ((size_t)1 << b); ++k) form.put(out, ((size_t)1 << b) + k, pw[k << (n - 1 - b)]);
 }
 
 int upload(hntt_ctx *ctx, const std::vector<uint64_t> &src, int bits, const void **out) {
@@ -241,9 +264,9 @@ int upload(hntt_ctx *ctx, const std::vector<uint64_t> &src, int bits, const void
   return HNTT_OK;
 }
 
-// Twiddle tables for one (p, omega, l, word_bits): built on the host once and kept on the device.
-int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const Tables **out) {
-  const auto key = std::make_tuple(p, omega, l, bits);
+// Twiddle tables for one (p, omega, l, word_bits, form): built on the host once and kept on the device.
+int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, const Tables **out) {
+  const auto key = std::make_tuple(p, omega, l, bits, mont);
   auto it = ctx->tables.find(key);
   if (it != ctx->tables.end()) {
     *out = &it->second;
@@ -251,15 +274,18 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const
   }
   Tables t{};
   t.plan = make_plan(l, bits);
+  t.mont = mont;
+  const TableForm form(p, bits, mont);
   const uint64_t omega_inv = powmod(omega, p - 2, p);
   const uint64_t L = 1ull << l;
   const uint64_t linv = powmod(L % p, p - 2, p);
-  t.linv = linv;
-  t.linv_p = shoup_constant(linv, p, bits);
+  t.linv = mont ? mulmod(linv, form.beta_mod_p, p) : linv;
+  t.linv_p = mont ? 0 : shoup_constant(linv, p, bits);
+  t.jinv = inv_mod_beta(p, bits);
   std::vector<uint64_t> tab;
   int rc;
   auto table = [&](uint64_t root, int n, const void **dst) -> int {
-    heap_table(root, n, p, bits, tab);
+    heap_table(root, n, form, tab);
     return upload(ctx, tab, bits, dst);
   };
   if (!t.plan.split) {
@@ -283,11 +309,8 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const
     const RoundSplit rs_c = pass_split(c, bits), rs_r = pass_split(r, bits);
     const int sf = c - rs_c.kh, si = rs_r.kl;
     const uint64_t Sf = (1ull << sf) + (1ull << (c - sf)), Si = (1ull << si) + (1ull << (r - si));
-    std::vector<uint64_t> f(2 * R * Sf), iv(2 * C * Si);
-    auto put = [&](std::vector<uint64_t> &v, uint64_t idx, uint64_t w) {
-      v[2 * idx] = w;
-      v[2 * idx + 1] = shoup_constant(w, p, bits);
-    };
+    std::vector<uint64_t> f(form.words() * R * Sf), iv(form.words() * C * Si);
+    auto put = [&](std::vector<uint64_t> &v, uint64_t idx, uint64_t w) { form.put(v, idx, w); };
     for (uint64_t B = 0; B < R; ++B) {
       const uint64_t ws = powmod(omega, bitrev((unsigned)B, r), p);  // omega^s
       const uint64_t wsh = powmod(ws, 1ull << sf, p);                 // omega^(s 2^sf)
@@ -326,8 +349,8 @@ int ensure_device(hntt_ctx *ctx) {
 std::string pass_name(const PassParams &pp) {
   const char *kind = pp.kind == PassKind::kWhole ? "whole" : pp.kind == PassKind::kRows ? "rows" : "cols";
   char buf[96];
-  snprintf(buf, sizeof buf, "%s_%s_%s_u%d_n%d", kind, pp.inverse ? "inv" : "fwd", pp.lazy ? "lazy" : "plain",
-           pp.word_bits, pp.n);
+  const char *pol = pp.policy == kPolicyMont ? "mont" : pp.policy == kPolicyLazy ? "lazy" : "plain";
+  snprintf(buf, sizeof buf, "%s_%s_%s_u%d_n%d", kind, pp.inverse ? "inv" : "fwd", pol, pp.word_bits, pp.n);
   return buf;
 }
 
@@ -351,7 +374,7 @@ hipError_t launch_traced(hntt_ctx *ctx, const PassParams &pp, const BatchPtrs &b
 // Run every pass of one transform direction over a batch sharing (p, omega, l, word_bits).
 int run_transform(hntt_ctx *ctx, const Tables &t, const Plan &plan, const std::vector<void *> &ptrs, uint64_t p,
                   int l, int bits, bool inverse, uint32_t flags, hipStream_t stream) {
-  const bool lazy = !(flags & HNTT_PLAIN);
+  const int policy = (flags & HNTT_PLAIN) ? kPolicyPlain : (flags & HNTT_MONT) ? kPolicyMont : kPolicyLazy;
   const bool norm = !(flags & HNTT_NO_NORMALIZE);
   const size_t chunk = (size_t)std::max(1, std::min(plan.chunk, kMaxBatchPerLaunch));
   for (size_t off = 0; off < ptrs.size(); off += chunk) {
@@ -360,10 +383,11 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const Plan &plan, const std::v
     for (int i = 0; i < nb; ++i) bp.ptr[i] = reinterpret_cast<uint64_t>(ptrs[off + i]);
     PassParams pp{};
     pp.word_bits = bits;
-    pp.lazy = lazy;
+    pp.policy = policy;
     pp.inverse = inverse;
     pp.nbatch = nb;
     pp.p = p;
+    pp.jinv = t.jinv;
     hipError_t e;
     if (!plan.split) {
       pp.kind = PassKind::kWhole;
@@ -409,7 +433,9 @@ int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, v
   if (!ctx) return HNTT_EINVAL;
   ctx->last_error.clear();
   if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
-  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE | HNTT_MONT)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  if ((flags & HNTT_PLAIN) && (flags & HNTT_MONT))
+    return set_error(ctx, HNTT_EINVAL, "HNTT_PLAIN and HNTT_MONT select different butterflies");
   // group descriptors that share parameters; validate everything before enqueueing anything
   std::map<std::tuple<uint64_t, uint64_t, int, int>, std::vector<void *>> groups;
   for (size_t i = 0; i < n; ++i) {
@@ -427,7 +453,7 @@ int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, v
     const uint64_t p = std::get<0>(kv.first), omega = std::get<1>(kv.first);
     const int l = std::get<2>(kv.first), bits = std::get<3>(kv.first);
     const Tables *t = nullptr;
-    if ((rc = get_tables(ctx, p, omega, l, bits, &t))) return rc;
+    if ((rc = get_tables(ctx, p, omega, l, bits, (flags & HNTT_MONT) != 0, &t))) return rc;
     const Plan plan = effective_plan(ctx, l, bits);
     if ((rc = run_transform(ctx, *t, plan, kv.second, p, l, bits, inverse, flags, (hipStream_t)stream))) return rc;
   }
@@ -486,7 +512,9 @@ int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flag
   if (!ctx) return HNTT_EINVAL;
   ctx->last_error.clear();
   if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
-  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE | HNTT_MONT)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  if ((flags & HNTT_PLAIN) && (flags & HNTT_MONT))
+    return set_error(ctx, HNTT_EINVAL, "HNTT_PLAIN and HNTT_MONT select different butterflies");
   for (size_t i = 0; i < n; ++i) {
     int rc = check_desc(ctx, descs[i], flags);
     if (rc) return rc;
@@ -621,7 +649,7 @@ int hntt_debug_butterfly(hntt_ctx *ctx, int kind, uint32_t word_bits, uint64_t p
                          const void *w, const void *wprime, void *xo, void *yo, size_t n, void *stream) {
   if (!ctx) return HNTT_EINVAL;
   ctx->last_error.clear();
-  if (kind < 0 || kind > 3) return set_error(ctx, HNTT_EINVAL, "kind must be 0..3");
+  if (kind < 0 || kind > 5) return set_error(ctx, HNTT_EINVAL, "kind must be 0..5");
   if (word_bits != 32 && word_bits != 64) return set_error(ctx, HNTT_EINVAL, "word_bits must be 32 or 64");
   if (n && (!x || !y || !w || !wprime || !xo || !yo)) return set_error(ctx, HNTT_EINVAL, "NULL array");
   const unsigned limit_bits = word_bits - ((kind == 0 || kind == 3) ? 1 : 2);

@@ -33,11 +33,14 @@ struct Plan {
   int chunk;   // transforms per launch; every pass runs on one chunk before the next chunk
 };
 
-// Device twiddle tables for one (p, omega, l, word_bits), each an array of
-// interleaved (W, W') pairs.
+// Device twiddle tables for one (p, omega, l, word_bits, form): arrays of
+// interleaved (W, W') pairs with W' = floor(W beta / p) (Shoup form), or of
+// single words W beta mod p (Montgomery form).
 struct Tables {
   Plan plan;
-  uint64_t linv, linv_p;                 // L^-1 mod p and its Shoup constant
+  bool mont;                             // Montgomery-form tables (single words W beta mod p)
+  uint64_t linv, linv_p;                 // L^-1 mod p and its Shoup constant (Montgomery: L^-1 beta mod p, 0)
+  uint64_t jinv;                         // p^-1 mod beta
   const void *fwd, *inv;                 // whole transform, or the column transform
   const void *row_fwd, *row_inv;         // row transform (split)
   const void *tt_fwd, *tt_inv;           // split twiddles (split)
@@ -65,7 +68,7 @@ struct hntt_ctx {
   bool device_ready = false;
   std::string last_error;
   std::map<uint64_t, bool> prime_cache;
-  std::map<std::tuple<uint64_t, uint64_t, int, int>, hntt::Tables> tables;
+  std::map<std::tuple<uint64_t, uint64_t, int, int, bool>, hntt::Tables> tables;
   std::map<std::pair<int, int>, hntt_tuning> tuning;  // (log2_len, word_bits) -> schedule override
   std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
   hntt_polymul_plan *poly_cache = nullptr;  // last plan of hntt_polymul_crt
@@ -89,7 +92,7 @@ Plan make_plan(int l, int word_bits);
 Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits);
 int check_tuning(const hntt_tuning &t, std::string *why);
 int ensure_device(hntt_ctx *ctx);
-int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, const Tables **out);
+int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, const Tables **out);
 // Launch wrapper that records HIP events around the launch when tracing is on.
 struct PassParams;
 hipError_t traced(hntt_ctx *ctx, const std::string &name, hipStream_t stream, hipError_t (*fn)(const void *, hipStream_t),

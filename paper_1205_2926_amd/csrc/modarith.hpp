@@ -58,6 +58,21 @@ __device__ __forceinline__ typename Wd::T shoup_lazy(typename Wd::T t, typename 
   return Wd::mullo(w, t) - Wd::mullo(q, p);
 }
 
+// Montgomery's product (the multiplication of Algorithm 5): for 0 <= t < beta,
+// W' = W beta mod p in [0,p) and J = p^-1 mod beta, the high word R1 of W' t is
+// below p; Q = (W' t mod beta) J mod beta makes Q p agree with W' t in the low
+// word, so W' t - Q p = beta (R1 - H) with H = floor(Q p / beta) < p, and
+// R1 - H + p lies in (0, 2p) and is congruent to W t mod p.
+template <class Wd>
+__device__ __forceinline__ typename Wd::T mont_lazy(typename Wd::T t, typename Wd::T wm, typename Wd::T p,
+                                                    typename Wd::T j) {
+  using T = typename Wd::T;
+  const T r0 = Wd::mullo(wm, t);
+  const T r1 = Wd::mulhi(wm, t);
+  const T q = Wd::mullo(r0, j);
+  return r1 - Wd::mulhi(q, p) + p;
+}
+
 // Algorithm 3 (lazy forward butterfly): X, Y in [0,2p), p < beta/4.
 // X' = X + Y reduced once to [0,2p); T = X - Y + 2p in [0,4p); Y' = W T in [0,2p).
 template <class Wd>
@@ -67,6 +82,18 @@ __device__ __forceinline__ void bfly_fwd_lazy(typename Wd::T &x, typename Wd::T 
   const T s = csub<T>(x + y, p2);
   const T t = x - y + p2;
   y = shoup_lazy<Wd>(t, w, wp, p);
+  x = s;
+}
+
+// Algorithm 5 (Montgomery forward butterfly): X, Y in [0,2p), p < beta/4, the
+// twiddle given only as W' = W beta mod p.  X' as in Algorithm 3; Y' = W T in [0,2p).
+template <class Wd>
+__device__ __forceinline__ void bfly_fwd_mont(typename Wd::T &x, typename Wd::T &y, typename Wd::T wm,
+                                              typename Wd::T p, typename Wd::T p2, typename Wd::T j) {
+  using T = typename Wd::T;
+  const T s = csub<T>(x + y, p2);
+  const T t = x - y + p2;
+  y = mont_lazy<Wd>(t, wm, p, j);
   x = s;
 }
 
@@ -114,6 +141,20 @@ __device__ __forceinline__ void bfly_inv_lazy(typename Wd::T &x, typename Wd::T 
   using T = typename Wd::T;
   const T xr = csub<T>(x, p2);
   const T t = shoup_lazy<Wd>(y, w, wp, p);
+  x = xr + t;
+  y = xr - t + p2;
+}
+
+// Inverse butterfly of the lazy [0,4p) range with Montgomery's product in place
+// of Shoup's (Section 4 notes that the lazy idea carries over to other modular
+// products): X reduced once to [0,2p); T = W Y in [0,2p) from W' = W beta mod p;
+// X' = X + T, Y' = X - T + 2p in [0,4p).
+template <class Wd>
+__device__ __forceinline__ void bfly_inv_mont(typename Wd::T &x, typename Wd::T &y, typename Wd::T wm,
+                                              typename Wd::T p, typename Wd::T p2, typename Wd::T j) {
+  using T = typename Wd::T;
+  const T xr = csub<T>(x, p2);
+  const T t = mont_lazy<Wd>(y, wm, p, j);
   x = xr + t;
   y = xr - t + p2;
 }

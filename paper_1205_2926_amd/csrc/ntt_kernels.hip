@@ -39,6 +39,8 @@ __global__ void k_debug_butterfly(int kind, uint64_t p64, const typename Wd::T *
     case 0: bfly_fwd_plain<Wd>(a, c, w[i], wp[i], p); break;
     case 1: bfly_fwd_lazy<Wd>(a, c, w[i], wp[i], p, p2); break;
     case 2: bfly_inv_lazy<Wd>(a, c, w[i], wp[i], p, p2); break;
+    case 4: bfly_fwd_mont<Wd>(a, c, w[i], p, p2, wp[i]); break;  // w = W beta mod p, wp = p^-1 mod beta
+    case 5: bfly_inv_mont<Wd>(a, c, w[i], p, p2, wp[i]); break;
     default: bfly_inv_plain<Wd>(a, c, w[i], wp[i], p); break;
   }
   xo[i] = a;

@@ -23,13 +23,23 @@ struct XformEntry {
 
 constexpr int kMaxSlots = 4;
 
+// Butterfly policy of a launch.
+enum : int {
+  kPolicyPlain = 0,  // Algorithm 2 and the fully reducing inverse (Shoup products)
+  kPolicyLazy = 1,   // Algorithms 3 and 4 (Shoup products, W and W' = floor(W beta / p))
+  kPolicyMont = 2,   // Algorithm 5 and its inverse (Montgomery products, W' = W beta mod p only)
+};
+
 // Per-prime launch parameters (tables built for the launch's sub-transform length).
+// Table entries are (W, W') pairs for the Shoup policies and single words
+// W beta mod p for the Montgomery policy.
 struct SlotParams {
   uint64_t p;
-  const void *tw;     // per-stage (W, W') pairs of omega_N^(+-j)
-  const void *tt;     // kCols: split twiddles, same shape as the data
-  uint64_t scale_w;   // kWhole inverse: L^-1 and its Shoup constant
-  uint64_t scale_wp;
+  const void *tw;     // per-stage twiddles of omega_N^(+-j)
+  const void *tt;     // split-twiddle factors of the pass (null when it has none)
+  uint64_t scale_w;   // kWhole inverse: L^-1 (Montgomery policy: L^-1 beta mod p)
+  uint64_t scale_wp;  // and its Shoup constant (unused by the Montgomery policy)
+  uint64_t jinv;      // Montgomery policy: p^-1 mod beta
 };
 
 // Which pass of the transform a launch performs.
@@ -71,7 +81,7 @@ inline int pass_tpt(int n, int word_bits) {
 struct PassParams {
   PassKind kind;
   int word_bits;   // 32 or 64
-  bool lazy;       // Algorithm 3/4 (true) or fully reducing (false)
+  int policy;      // kPolicyPlain, kPolicyLazy or kPolicyMont
   bool inverse;    // Algorithm 1 forward (false) or run backwards (true)
   bool normalize;  // reduce the final output to [0,p)
   int n;           // log2 of the sub-transform length handled inside a workgroup
@@ -79,10 +89,11 @@ struct PassParams {
   int group;       // sub-transforms per workgroup
   int nbatch;      // transforms in this launch (<= kMaxBatchPerLaunch unless `table` is set)
   uint64_t p;
-  const void *tw;     // interleaved (W, W') pairs of omega_N^(+-j), j < 2^(n-1)
-  const void *tt;     // kCols: interleaved split twiddles, same shape as the data
-  uint64_t scale_w;   // kWhole inverse: L^-1 and its Shoup constant
-  uint64_t scale_wp;
+  const void *tw;     // per-stage twiddle table of the sub-transform (heap order)
+  const void *tt;     // split-twiddle factors of the second pass of a transform, else null
+  uint64_t scale_w;   // kWhole inverse: L^-1 (Montgomery policy: L^-1 beta mod p)
+  uint64_t scale_wp;  // and its Shoup constant
+  uint64_t jinv;      // Montgomery policy: p^-1 mod beta
   // Batched form: transforms listed in a device table, each with its prime's slot;
   // when `table` is set, p/tw/tt/scale above are ignored and slots[] is used.
   const XformEntry *table;

@@ -94,42 +94,76 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t vof
     __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, 0);
   }
 }
-__device__ __forceinline__ Tw2 buf_load_tw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  Tw2 w;
-  if constexpr (sizeof(T) == 4) {
-    typedef int V2 __attribute__((ext_vector_type(2)));
-    const V2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
-    w.x = (T)(uint32_t)v.x;
-    w.y = (T)(uint32_t)v.y;
+// Twiddle table entry of a policy: (W, W') pair for Shoup products, the single
+// word W beta mod p for Montgomery products.
+template <int Pol>
+struct TwOf {
+  using type = Tw2;
+};
+template <>
+struct TwOf<kPolicyMont> {
+  using type = T;
+};
+template <int Pol>
+using TwT = typename TwOf<Pol>::type;
+
+template <int Pol>
+__device__ __forceinline__ TwT<Pol> buf_load_tw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (Pol == kPolicyMont) {
+    return buf_load(r, voff, soff);
   } else {
-    typedef int V4 __attribute__((ext_vector_type(4)));
-    const V4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
-    w.x = (T)(uint32_t)v.x | ((T)(uint32_t)v.y << 32);
-    w.y = (T)(uint32_t)v.z | ((T)(uint32_t)v.w << 32);
+    Tw2 w;
+    if constexpr (sizeof(T) == 4) {
+      typedef int V2 __attribute__((ext_vector_type(2)));
+      const V2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+      w.x = (T)(uint32_t)v.x;
+      w.y = (T)(uint32_t)v.y;
+    } else {
+      typedef int V4 __attribute__((ext_vector_type(4)));
+      const V4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+      w.x = (T)(uint32_t)v.x | ((T)(uint32_t)v.y << 32);
+      w.y = (T)(uint32_t)v.z | ((T)(uint32_t)v.w << 32);
+    }
+    return w;
   }
-  return w;
 }
 
-template <bool Lazy>
-__device__ __forceinline__ void bfly(T &x, T &y, T w, T wp, T p, T p2) {
-  if constexpr (kInverse) {
-    if constexpr (Lazy) bfly_inv_lazy<Wd>(x, y, w, wp, p, p2);
-    else bfly_inv_plain<Wd>(x, y, w, wp, p);
+// The modulus of a launch: p, 2p and (Montgomery policy) p^-1 mod beta.
+struct Mod {
+  T p, p2, j;
+};
+
+template <int Pol>
+__device__ __forceinline__ void bfly(T &x, T &y, const TwT<Pol> &tw, const Mod &m) {
+  if constexpr (Pol == kPolicyMont) {
+    if constexpr (kInverse) bfly_inv_mont<Wd>(x, y, tw, m.p, m.p2, m.j);
+    else bfly_fwd_mont<Wd>(x, y, tw, m.p, m.p2, m.j);
+  } else if constexpr (kInverse) {
+    if constexpr (Pol == kPolicyLazy) bfly_inv_lazy<Wd>(x, y, tw.x, tw.y, m.p, m.p2);
+    else bfly_inv_plain<Wd>(x, y, tw.x, tw.y, m.p);
   } else {
-    if constexpr (Lazy) bfly_fwd_lazy<Wd>(x, y, w, wp, p, p2);
-    else bfly_fwd_plain<Wd>(x, y, w, wp, p);
+    if constexpr (Pol == kPolicyLazy) bfly_fwd_lazy<Wd>(x, y, tw.x, tw.y, m.p, m.p2);
+    else bfly_fwd_plain<Wd>(x, y, tw.x, tw.y, m.p);
   }
 }
 
-template <bool Lazy>
-__device__ __forceinline__ void bfly_w1(T &x, T &y, T p, T p2) {
+// Butterfly whose twiddle is 1: no product (both lazy policies share the ranges).
+template <int Pol>
+__device__ __forceinline__ void bfly_w1(T &x, T &y, const Mod &m) {
   if constexpr (kInverse) {
-    if constexpr (Lazy) bfly_inv_lazy_w1<Wd>(x, y, p2);
-    else bfly_inv_plain_w1<Wd>(x, y, p);
+    if constexpr (Pol != kPolicyPlain) bfly_inv_lazy_w1<Wd>(x, y, m.p2);
+    else bfly_inv_plain_w1<Wd>(x, y, m.p);
   } else {
-    if constexpr (Lazy) bfly_fwd_lazy_w1<Wd>(x, y, p2);
-    else bfly_fwd_plain_w1<Wd>(x, y, p);
+    if constexpr (Pol != kPolicyPlain) bfly_fwd_lazy_w1<Wd>(x, y, m.p2);
+    else bfly_fwd_plain_w1<Wd>(x, y, m.p);
   }
+}
+
+// x (any word) times a table constant, result in [0,2p).
+template <int Pol>
+__device__ __forceinline__ T mul_const(T x, const TwT<Pol> &tw, const Mod &m) {
+  if constexpr (Pol == kPolicyMont) return mont_lazy<Wd>(x, tw, m.p, m.j);
+  else return shoup_lazy<Wd>(x, tw.x, tw.y, m.p);
 }
 
 // Words per 16-byte vector access.
@@ -145,9 +179,10 @@ constexpr int kVec = 16 / sizeof(T);
 // Src/Dst provide load2/store2 of one position given as a per-lane part plus a
 // uniform part with disjoint bits, and load_vec/store_vec of kVec consecutive
 // positions when their kContig flag is set.
-template <bool Lazy, int N_LOG, int K, bool LowRound, class Src, class Dst>
-__device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws, const HNTT_GLOBAL Tw2 *__restrict__ twg, T p,
-                                       T p2, const Src &src, const Dst &dst) {
+template <int Pol, int N_LOG, int K, bool LowRound, class Src, class Dst>
+__device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol> *tws,
+                                       const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m, const Src &src,
+                                       const Dst &dst) {
   constexpr int groups = 1 << (N_LOG - K);
   constexpr int M = 1 << K;
 #pragma unroll 1
@@ -171,16 +206,16 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws
         if constexpr (LowRound) {
           const int kk = e & ((1 << hb) - 1);
           if (kk == 0) {
-            bfly_w1<Lazy>(v[e], v[e | (1 << hb)], p, p2);
+            bfly_w1<Pol>(v[e], v[e | (1 << hb)], m);
           } else {
-            const Tw2 tw = twg[(1 << hb) + kk];
-            bfly<Lazy>(v[e], v[e | (1 << hb)], tw.x, tw.y, p, p2);
+            const TwT<Pol> tw = twg[(1 << hb) + kk];
+            bfly<Pol>(v[e], v[e | (1 << hb)], tw, m);
           }
         } else {
           const int b = b_lo + hb;
           const int pos = base | (e << b_lo);
-          const Tw2 tw = tws[(1 << b) + (pos & ((1 << b) - 1))];
-          bfly<Lazy>(v[e], v[e | (1 << hb)], tw.x, tw.y, p, p2);
+          const TwT<Pol> tw = tws[(1 << b) + (pos & ((1 << b) - 1))];
+          bfly<Pol>(v[e], v[e | (1 << hb)], tw, m);
         }
       }
     }
@@ -195,9 +230,9 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const Tw2 *tws
 }
 
 // Final reduction of a lazy result: forward outputs lie in [0,2p), inverse in [0,4p).
-template <bool Lazy>
+template <int Pol>
 __device__ __forceinline__ T reduce_final(T x, T p) {
-  if constexpr (!Lazy) return x;
+  if constexpr (Pol == kPolicyPlain) return x;
   if constexpr (kInverse) x = csub<T>(x, p + p);
   return csub<T>(x, p);
 }
@@ -225,9 +260,9 @@ struct KernelArgs {
 // small enough to stay in the L1/L2 caches.  SIGMA is the bit boundary of the
 // pass's first register round, so one factor is fixed per thread group and the
 // other is shared by all lanes of a sub-transform.  TT = false: no split twiddle.
-template <bool Lazy, bool Cols, bool TT, int N_LOG, int SIGMA>
+template <int Pol, bool Cols, bool TT, int N_LOG, int SIGMA>
 struct Edge {
-  T p;
+  Mod m;
   int normalize, scale;
   T sw, swp;
   __amdgpu_buffer_rsrc_t tt;  // factor tables of the pass
@@ -237,12 +272,13 @@ struct Edge {
   __device__ __forceinline__ T in(T x, int lp, int up) const {
     if constexpr (TT) {
       constexpr int kMask = (1 << SIGMA) - 1;
-      const Tw2 hi = buf_load_tw(tt, tt_off + (uint32_t)((1 << SIGMA) + (lp >> SIGMA)) * tt_step,
-                                 (uint32_t)(up >> SIGMA) * tt_step);
-      const Tw2 lo = buf_load_tw(tt, tt_off + (uint32_t)(lp & kMask) * tt_step, (uint32_t)(up & kMask) * tt_step);
-      x = shoup_lazy<Wd>(x, hi.x, hi.y, p);  // any input < beta -> [0,2p)
-      x = shoup_lazy<Wd>(x, lo.x, lo.y, p);
-      if constexpr (!Lazy) x = csub<T>(x, p);
+      const TwT<Pol> hi = buf_load_tw<Pol>(tt, tt_off + (uint32_t)((1 << SIGMA) + (lp >> SIGMA)) * tt_step,
+                                           (uint32_t)(up >> SIGMA) * tt_step);
+      const TwT<Pol> lo = buf_load_tw<Pol>(tt, tt_off + (uint32_t)(lp & kMask) * tt_step,
+                                           (uint32_t)(up & kMask) * tt_step);
+      x = mul_const<Pol>(x, hi, m);  // any input < beta -> [0,2p)
+      x = mul_const<Pol>(x, lo, m);
+      if constexpr (Pol == kPolicyPlain) x = csub<T>(x, m.p);
     }
     return x;
   }
@@ -250,13 +286,14 @@ struct Edge {
   __device__ __forceinline__ T out(T x, int pos) const {
     if constexpr (!Cols && kInverse) {
       if (scale) {  // whole inverse transform: times L^-1, then reduced
-        x = shoup_lazy<Wd>(x, sw, swp, p);
-        if (normalize) x = csub<T>(x, p);
+        if constexpr (Pol == kPolicyMont) x = mont_lazy<Wd>(x, sw, m.p, m.j);
+        else x = shoup_lazy<Wd>(x, sw, swp, m.p);
+        if (normalize) x = csub<T>(x, m.p);
       } else if (normalize) {
-        x = reduce_final<Lazy>(x, p);
+        x = reduce_final<Pol>(x, m.p);
       }
     } else {
-      if (normalize) x = reduce_final<Lazy>(x, p);
+      if (normalize) x = reduce_final<Pol>(x, m.p);
     }
     return x;
   }
@@ -266,7 +303,7 @@ struct Edge {
 // of the transform at `base`.  The base is uniform across the workgroup (scalar
 // registers) and the offset is 32-bit, so accesses use the scalar-base addressing
 // form instead of per-lane 64-bit address arithmetic.
-template <bool Lazy, bool Cols, class EdgeT>
+template <bool Cols, class EdgeT>
 struct GlobalIO {
   static constexpr bool kContig = !Cols;
   HNTT_GLOBAL T *base;
@@ -344,7 +381,7 @@ constexpr int padded_len(int N) {
   return Cols ? N + N / 32 : N + (N >= 32 ? N / 8 : 0);
 }
 
-template <bool Lazy, bool Cols, int KH, int KM, int KL, bool TT>
+template <int Pol, bool Cols, int KH, int KM, int KL, bool TT>
 __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   constexpr int N_LOG = KH + KM + KL;
   // bit boundary of the first register round (split-twiddle factorisation)
@@ -365,7 +402,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     g = threadIdx.x / TPT;
   }
   const size_t C = (size_t)1 << a.log_other;
-  Tw2 *tws = reinterpret_cast<Tw2 *>(smem_raw);
+  TwT<Pol> *tws = reinterpret_cast<TwT<Pol> *>(smem_raw);
   T *tile = reinterpret_cast<T *>(tws + N);
 
   // One tile (transform b, unit) per workgroup.  Blocks are dealt to the 8 XCDs
@@ -397,17 +434,19 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     if (slot == 1) sp = a.slots[1];
     else if (slot == 2) sp = a.slots[2];
     else if (slot == 3) sp = a.slots[3];
-    const T p = (T)sp.p, p2 = p + p;
-    const HNTT_GLOBAL Tw2 *__restrict__ twg = (const HNTT_GLOBAL Tw2 *)(sp.tw);
+    const T p = (T)sp.p;
+    const Mod m{p, p + p, (T)sp.jinv};
+    const HNTT_GLOBAL TwT<Pol> *__restrict__ twg = (const HNTT_GLOBAL TwT<Pol> *)(sp.tw);
 
     HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(uniform64(ptr));
-    using EdgeT = Edge<Lazy, Cols, TT, N_LOG, SIGMA>;
-    EdgeT edge{p, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, make_rsrc(sp.tt, 0), 0, 0};
-    GlobalIO<Lazy, Cols, EdgeT> gio;
+    using EdgeT = Edge<Pol, Cols, TT, N_LOG, SIGMA>;
+    EdgeT edge{m, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, make_rsrc(sp.tt, 0), 0, 0};
+    GlobalIO<Cols, EdgeT> gio;
+    constexpr uint32_t kTw = sizeof(TwT<Pol>);
     constexpr uint32_t kTTStride = (1u << SIGMA) + (1u << (N_LOG - SIGMA));
     const uint32_t nsub = Cols ? (uint32_t)C : (1u << a.log_other);  // sub-transforms per transform
     if constexpr (TT)
-      edge.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt), nsub * kTTStride * (uint32_t)sizeof(Tw2));
+      edge.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt), nsub * kTTStride * kTw);
     gio.base = gbase;
     if constexpr (Cols) {
       const uint32_t col = (uint32_t)unit * G + g;
@@ -415,39 +454,39 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
       gio.off = col;
       gio.stride = (uint32_t)C;
       // factor-major table [factor][column]: adjacent columns' factors are adjacent
-      edge.tt_off = col * (uint32_t)sizeof(Tw2);
-      edge.tt_step = (uint32_t)C * (uint32_t)sizeof(Tw2);
+      edge.tt_off = col * kTw;
+      edge.tt_step = (uint32_t)C * kTw;
     } else {
       const uint32_t row = (uint32_t)unit * G + g;
       gio.off = row * N;
       gio.stride = 1;
       // row-major table [row][factor]: a row's lanes read consecutive low factors
-      edge.tt_off = row * kTTStride * (uint32_t)sizeof(Tw2);
-      edge.tt_step = (uint32_t)sizeof(Tw2);
+      edge.tt_off = row * kTTStride * kTw;
+      edge.tt_step = kTw;
     }
     gio.edge = edge;
 
     if constexpr (KH == 0) {
       // one round, HBM to HBM
-      round_k<Lazy, N_LOG, KL, true>(0, t, TPT, nullptr, twg, p, p2, gio, gio);
+      round_k<Pol, N_LOG, KL, true>(0, t, TPT, nullptr, twg, m, gio, gio);
     } else {
       for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = twg[i];
       const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
       if constexpr (!kInverse) {
         __syncthreads();  // twiddle table staged
-        round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, gio, lio);
+        round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio);
         __syncthreads();
         if constexpr (KM > 0) {
-          round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
+          round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
         }
         if constexpr (Cols) {
-          round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, gio);
+          round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, gio);
         } else {
           // Rows: a thread's low-round outputs are 2^KL consecutive words, so direct
           // stores would put neighbouring lanes 2^KL words apart.  Stage them in LDS
           // and write the tile out with consecutive lanes on consecutive 16 bytes.
-          round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, lio, lio);
+          round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
           constexpr int kPitch = padded_len<false>(N);
           constexpr int kChunks = N / kVec;
@@ -464,48 +503,48 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           }
         }
       } else {
-        round_k<Lazy, N_LOG, KL, true>(0, t, TPT, tws, twg, p, p2, gio, lio);
+        round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, gio, lio);
         __syncthreads();  // tile and twiddle table complete
         if constexpr (KM > 0) {
-          round_k<Lazy, N_LOG, KM, false>(KL, t, TPT, tws, twg, p, p2, lio, lio);
+          round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
         }
-        round_k<Lazy, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, p, p2, lio, gio);
+        round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, lio, gio);
       }
     }
   }
 }
 
-template <bool Lazy, bool Cols, int KH, int KM, int KL, bool TT>
+template <int Pol, bool Cols, int KH, int KM, int KL, bool TT>
 hipError_t launch_k(const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<Lazy, Cols, KH, KM, KL, TT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<Pol, Cols, KH, KM, KL, TT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL((k_pass<Lazy, Cols, KH, KM, KL, TT>), dim3(blocks), dim3(threads), lds, stream, a);
+  hipLaunchKernelGGL((k_pass<Pol, Cols, KH, KM, KL, TT>), dim3(blocks), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 
 // The split twiddle exists only in the second pass of a transform: the inverse
 // column pass and the forward row pass of a split transform.
-template <bool Lazy, bool Cols, int KH, int KM, int KL>
+template <int Pol, bool Cols, int KH, int KM, int KL>
 hipError_t launch_tt(bool tt, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t stream) {
   if constexpr (Cols != kInverse) {
     (void)tt;
-    return launch_k<Lazy, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
+    return launch_k<Pol, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
   } else {
-    return tt ? launch_k<Lazy, Cols, KH, KM, KL, true>(a, blocks, threads, lds, stream)
-              : launch_k<Lazy, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
+    return tt ? launch_k<Pol, Cols, KH, KM, KL, true>(a, blocks, threads, lds, stream)
+              : launch_k<Pol, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
   }
 }
 
 // Round splits per word size; must agree with pass_split().
-template <bool Lazy, bool Cols>
+template <int Pol, bool Cols>
 hipError_t dispatch_n(int n, bool tt, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t s) {
 #define HNTT_CASE(N, KH, KM, KL) \
-  case N: return launch_tt<Lazy, Cols, KH, KM, KL>(tt, a, blocks, threads, lds, s);
+  case N: return launch_tt<Pol, Cols, KH, KM, KL>(tt, a, blocks, threads, lds, s);
   switch (n) {
     HNTT_CASE(1, 0, 0, 1)
     HNTT_CASE(2, 0, 0, 2)
@@ -573,15 +612,24 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   if (pp.table) {
     for (int i = 0; i < pp.nslots; ++i) a.slots[i] = pp.slots[i];
   } else {
-    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp};
+    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp, pp.jinv};
   }
   const int blocks = (int)total;
   using namespace HNTT_NS;
   const bool tt = pp.table ? pp.slots[0].tt != nullptr : pp.tt != nullptr;
-  if (pp.lazy) return cols ? dispatch_n<true, true>(n, tt, a, blocks, threads, lds, stream)
-                           : dispatch_n<true, false>(n, tt, a, blocks, threads, lds, stream);
-  return cols ? dispatch_n<false, true>(n, tt, a, blocks, threads, lds, stream)
-              : dispatch_n<false, false>(n, tt, a, blocks, threads, lds, stream);
+  switch (pp.policy) {
+    case kPolicyLazy:
+      return cols ? dispatch_n<kPolicyLazy, true>(n, tt, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyLazy, false>(n, tt, a, blocks, threads, lds, stream);
+    case kPolicyPlain:
+      return cols ? dispatch_n<kPolicyPlain, true>(n, tt, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyPlain, false>(n, tt, a, blocks, threads, lds, stream);
+    case kPolicyMont:
+      return cols ? dispatch_n<kPolicyMont, true>(n, tt, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyMont, false>(n, tt, a, blocks, threads, lds, stream);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace hntt

@@ -136,7 +136,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t 
   if (count == 0) return HNTT_OK;
   PassParams base{};
   base.word_bits = 32;
-  base.lazy = !(flags & HNTT_PLAIN);
+  base.policy = (flags & HNTT_PLAIN) ? kPolicyPlain : kPolicyLazy;
   base.inverse = inverse;
   base.nbatch = count;
   base.table = table;
@@ -148,6 +148,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t 
       sp.p = kPrimes[k];
       sp.scale_w = t.linv;
       sp.scale_wp = t.linv_p;
+      sp.jinv = t.jinv;
       sp.tt = nullptr;
       // the split twiddle enters with the second pass: rows (forward), columns (inverse)
       if (which == 0) sp.tw = inverse ? t.inv : t.fwd;               // whole
@@ -255,7 +256,7 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
     for (int k = 0; k < 3; ++k) {
       const uint64_t q = kPrimes[k];
       const uint64_t omega = powmod(primitive_root(q), (q - 1) >> l, q);
-      if ((rc = get_tables(ctx, q, omega, l, 32, &cw.tab[k]))) return rc;
+      if ((rc = get_tables(ctx, q, omega, l, 32, false, &cw.tab[k]))) return rc;
     }
     classes.push_back(cw);
   }

@@ -24,6 +24,8 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5
 PLAIN = 0x1
 NO_NORMALIZE = 0x2
 NO_GRAPH = 0x4
+MONT = 0x8
+POLICY_FLAGS = {"lazy": 0, "plain": PLAIN, "mont": MONT}
 
 _c_u64 = ctypes.c_uint64
 _c_u32 = ctypes.c_uint32
@@ -255,20 +257,23 @@ class Context:
         return [x] if x.dim() == 1 else list(x.reshape(-1, x.shape[-1]).unbind(0))
 
     # -- transforms --------------------------------------------------------------------------------
-    def ntt_forward(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None):
-        """In-place forward NTT of every row of x (natural in, bit-reversed out)."""
-        self._transform(self.lib.hntt_ntt_forward, x, p, omega, plain, normalize, stream)
+    def ntt_forward(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None,
+                    mont: bool = False):
+        """In-place forward NTT of every row of x (natural in, bit-reversed out).  plain selects
+        Algorithm 2, mont Algorithm 5; the default is Algorithm 3."""
+        self._transform(self.lib.hntt_ntt_forward, x, p, omega, plain, normalize, stream, mont)
         return x
 
-    def ntt_inverse(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None):
+    def ntt_inverse(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None,
+                    mont: bool = False):
         """In-place inverse NTT of every row of x (bit-reversed in, natural out, times L^-1)."""
-        self._transform(self.lib.hntt_ntt_inverse, x, p, omega, plain, normalize, stream)
+        self._transform(self.lib.hntt_ntt_inverse, x, p, omega, plain, normalize, stream, mont)
         return x
 
-    def _transform(self, fn, x, p, omega, plain, normalize, stream):
+    def _transform(self, fn, x, p, omega, plain, normalize, stream, mont=False):
         rows = self.rows_of(x) if isinstance(x, torch.Tensor) else list(x)
         arr = self.descs(rows, p, omega)
-        flags = (PLAIN if plain else 0) | (0 if normalize else NO_NORMALIZE)
+        flags = (PLAIN if plain else 0) | (MONT if mont else 0) | (0 if normalize else NO_NORMALIZE)
         dev = rows[0].device if rows else torch.device("cuda", self.device)
         self._check(fn(self.handle, arr, len(rows), flags, _stream_handle(stream, dev)))
 

@@ -124,6 +124,17 @@ def test_plain_allows_larger_primes(ctx):
     assert ctx.validate(arr, hntt.PLAIN) == hntt.OK
 
 
+def test_montgomery_flag_checks(ctx):
+    """Algorithm 5 has the lazy bound p < beta/4; HNTT_PLAIN and HNTT_MONT exclude each other."""
+    arr = _desc()
+    assert ctx.validate(arr, hntt.MONT) == hntt.OK
+    assert ctx.validate(arr, hntt.MONT | hntt.PLAIN) == hntt.EINVAL
+    assert "HNTT_MONT" in ctx.last_error()
+    p = 2013265921  # < beta/2 but not < beta/4
+    assert ctx.validate(_desc(p=p, omega=pow(31, (p - 1) >> 10, p)), hntt.MONT) == hntt.EUNSUPPORTED
+    assert ctx.validate(arr, 0x10) == hntt.EINVAL
+
+
 def test_composite_modulus_rejected(ctx):
     # 3 * 2^30 + 1 = 3221225473 is composite (and above beta/4 anyway), 7 * 2^20 + 1 = 7340033 is prime
     n = 5 * 7340033  # composite, odd, = 1 mod 2^? small

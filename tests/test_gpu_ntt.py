@@ -38,9 +38,16 @@ def _omega(orc, p, g, l):
     return w
 
 
+POLICIES = ["lazy", "plain", "mont"]  # Algorithms 3/4, 2, and 5 (with its inverse counterpart)
+
+
+def _kw(policy):
+    return {"plain": policy == "plain", "mont": policy == "mont"}
+
+
 # ---------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("plain", [False, True], ids=["lazy", "plain"])
-def test_single_1k(ctx, orc, plain):
+@pytest.mark.parametrize("policy", POLICIES)
+def test_single_1k(ctx, orc, policy):
     """One forward NTT of 1024 residues mod 998244353 with omega = 3^((p-1)/1024):
     bit-exact against the oracle and the naive DFT, output bit-reversed in [0,p)."""
     cfg = SINGLE_1K
@@ -48,12 +55,12 @@ def test_single_1k(ctx, orc, plain):
     w = _omega(orc, cfg.p, cfg.g, cfg.log2_len)
     assert w == 258648936
     t = dev(x)
-    ctx.ntt_forward(t, cfg.p, w, plain=plain)
+    ctx.ntt_forward(t, cfg.p, w, **_kw(policy))
     got = host(t, np.uint32)
     ref = orc.forward(x, cfg.log2_len, cfg.p, w)
     np.testing.assert_array_equal(got.astype(np.uint64), ref)
     assert got.tolist() == to_bitrev(naive_dft(x.tolist(), cfg.p, w))
-    ctx.ntt_inverse(t, cfg.p, w, plain=plain)
+    ctx.ntt_inverse(t, cfg.p, w, **_kw(policy))
     np.testing.assert_array_equal(host(t, np.uint32), x)
 
 
@@ -61,23 +68,23 @@ LENGTHS_32 = [(l, P30, G30) for l in range(1, 24)] + [(24, 167772161, 3)]
 LENGTHS_64 = [(l, P62, G62) for l in range(1, 23)]
 
 
-@pytest.mark.parametrize("plain", [False, True], ids=["lazy", "plain"])
+@pytest.mark.parametrize("policy", POLICIES)
 @pytest.mark.parametrize("wb,l,p,g", [(32, *c) for c in LENGTHS_32] + [(64, *c) for c in LENGTHS_64],
                          ids=lambda v: str(v))
-def test_every_length(ctx, orc, wb, l, p, g, plain):
+def test_every_length(ctx, orc, wb, l, p, g, policy):
     """Forward and inverse at every length from 2 up to the two-pass limit, several
     tiles and ragged batch sizes, against the oracle."""
     batch = 3 if l <= 14 else 1
     w = _omega(orc, p, g, l)
     x = uniform_residues(100 + l, (batch, 1 << l), p, _np_dtype(wb))
     t = dev(x)
-    ctx.ntt_forward(t, p, w, plain=plain)
+    ctx.ntt_forward(t, p, w, **_kw(policy))
     np.testing.assert_array_equal(host(t, _np_dtype(wb)).astype(np.uint64), orc.forward(x, l, p, w))
     y = uniform_residues(200 + l, (batch, 1 << l), p, _np_dtype(wb))
     u = dev(y)
-    ctx.ntt_inverse(u, p, w, plain=plain)
+    ctx.ntt_inverse(u, p, w, **_kw(policy))
     np.testing.assert_array_equal(host(u, _np_dtype(wb)).astype(np.uint64), orc.inverse(y, l, p, w))
-    ctx.ntt_forward(u, p, w, plain=plain)
+    ctx.ntt_forward(u, p, w, **_kw(policy))
     np.testing.assert_array_equal(host(u, _np_dtype(wb)), y)
 
 
@@ -90,26 +97,30 @@ def _sampled_points(orc, x, got, l, p, w, per_row, seed):
 
 def test_headline_batch64_lazy_vs_plain(ctx, orc):
     """64 forward+inverse NTTs of length 2^20 mod 998244353 (the benchmark's workload, same
-    launches): lazy and plain agree bit for bit, whole transforms match the oracle on a
-    subset, every transform matches the definition at sampled outputs, and the round trip
-    returns the input exactly."""
+    launches): lazy, plain and Montgomery agree bit for bit, whole transforms match the
+    oracle on a subset, every transform matches the definition at sampled outputs, and the
+    round trip returns the input exactly."""
     cfg = BATCH64_1M
     x = cfg.data()
     l, p = cfg.log2_len, cfg.p
     w = _omega(orc, p, cfg.g, l)
     assert w == 565042129
-    t_lazy, t_plain = dev(x), dev(x)
+    t_lazy, t_plain, t_mont = dev(x), dev(x), dev(x)
     ctx.ntt_forward(t_lazy, p, w)
     ctx.ntt_forward(t_plain, p, w, plain=True)
+    ctx.ntt_forward(t_mont, p, w, mont=True)
     got = host(t_lazy, np.uint32)
     np.testing.assert_array_equal(got, host(t_plain, np.uint32))
+    np.testing.assert_array_equal(got, host(t_mont, np.uint32))
     for b in (0, 17, 63):
         np.testing.assert_array_equal(got[b].astype(np.uint64), orc.forward(x[b], l, p, w))
     _sampled_points(orc, x, got, l, p, w, per_row=3, seed=5)
     ctx.ntt_inverse(t_lazy, p, w)
     ctx.ntt_inverse(t_plain, p, w, plain=True)
+    ctx.ntt_inverse(t_mont, p, w, mont=True)
     np.testing.assert_array_equal(host(t_lazy, np.uint32), x)
     np.testing.assert_array_equal(host(t_plain, np.uint32), x)
+    np.testing.assert_array_equal(host(t_mont, np.uint32), x)
 
 
 def test_u64_batch8(ctx, orc):
@@ -121,14 +132,19 @@ def test_u64_batch8(ctx, orc):
     assert w == 3217870244631358983
     t = dev(x)
     tp = dev(x)
+    tm = dev(x)
     ctx.ntt_forward(t, p, w)
     ctx.ntt_forward(tp, p, w, plain=True)
+    ctx.ntt_forward(tm, p, w, mont=True)
     got = host(t, np.uint64)
     np.testing.assert_array_equal(got, host(tp, np.uint64))
+    np.testing.assert_array_equal(got, host(tm, np.uint64))
     np.testing.assert_array_equal(got[0], orc.forward(x[0], l, p, w))
     _sampled_points(orc, x, got, l, p, w, per_row=2, seed=6)
     ctx.ntt_inverse(t, p, w)
     np.testing.assert_array_equal(host(t, np.uint64), x)
+    ctx.ntt_inverse(tm, p, w, mont=True)
+    np.testing.assert_array_equal(host(tm, np.uint64), x)
 
 
 def test_mixed_batch_one_call(ctx, orc):
@@ -160,9 +176,9 @@ def test_closed_forms_and_extremes(ctx, orc, l):
         "ones": np.ones(L, np.uint32),
     }
     for name, x in cases.items():
-        for plain in (False, True):
+        for policy in POLICIES:
             t = dev(x)
-            ctx.ntt_forward(t, p, w, plain=plain)
+            ctx.ntt_forward(t, p, w, **_kw(policy))
             got = host(t, np.uint32)
             np.testing.assert_array_equal(got.astype(np.uint64), orc.forward(x, l, p, w), err_msg=name)
             if name == "delta0":
@@ -171,37 +187,39 @@ def test_closed_forms_and_extremes(ctx, orc, l):
                 assert got[0] == L % p and not np.any(got[1:])
 
 
-def test_lazy_accepts_redundant_inputs(ctx, orc):
-    """Algorithm 3 takes inputs in [0,2p) and Algorithm 4 in [0,4p): redundant
-    representatives give the same fully reduced result."""
+@pytest.mark.parametrize("policy", ["lazy", "mont"])
+def test_lazy_accepts_redundant_inputs(ctx, orc, policy):
+    """Algorithms 3 and 5 take inputs in [0,2p) and the inverse butterflies in [0,4p):
+    redundant representatives give the same fully reduced result."""
     p, l = P30, 20
     w = _omega(orc, p, G30, l)
     x = uniform_residues(7, 1 << l, p, np.uint32)
     rng = np.random.Generator(np.random.PCG64(8))
     red = (x.astype(np.uint64) + p * rng.integers(0, 2, size=x.size, dtype=np.uint64)).astype(np.uint32)
     t = dev(red)
-    ctx.ntt_forward(t, p, w)
+    ctx.ntt_forward(t, p, w, **_kw(policy))
     np.testing.assert_array_equal(host(t, np.uint32).astype(np.uint64), orc.forward(x, l, p, w))
     red4 = (x.astype(np.uint64) + p * rng.integers(0, 4, size=x.size, dtype=np.uint64)).astype(np.uint32)
     u = dev(red4)
-    ctx.ntt_inverse(u, p, w)
+    ctx.ntt_inverse(u, p, w, **_kw(policy))
     np.testing.assert_array_equal(host(u, np.uint32).astype(np.uint64), orc.inverse(x, l, p, w))
 
 
+@pytest.mark.parametrize("policy", ["lazy", "mont"])
 @pytest.mark.parametrize("l", [10, 20])
-def test_no_normalize_ranges(ctx, orc, l):
+def test_no_normalize_ranges(ctx, orc, l, policy):
     """Without the final reduction the lazy forward result lies in [0,2p) and the inverse
-    in [0,4p) (Theorems 2 and 3), congruent to the oracle's."""
+    in [0,4p) (Theorems 2, 3 and 4), congruent to the oracle's."""
     p = P30
     w = _omega(orc, p, G30, l)
     x = uniform_residues(9, 1 << l, p, np.uint32)
     t = dev(x)
-    ctx.ntt_forward(t, p, w, normalize=False)
+    ctx.ntt_forward(t, p, w, normalize=False, **_kw(policy))
     got = host(t, np.uint32).astype(np.uint64)
     assert got.max() < 2 * p
     np.testing.assert_array_equal(got % p, orc.forward(x, l, p, w))
     u = dev(x)
-    ctx.ntt_inverse(u, p, w, normalize=False)
+    ctx.ntt_inverse(u, p, w, normalize=False, **_kw(policy))
     got = host(u, np.uint32).astype(np.uint64)
     assert got.max() < 4 * p
     np.testing.assert_array_equal(got % p, orc.inverse(x, l, p, w))
@@ -218,18 +236,19 @@ def test_deterministic(ctx):
 
 
 # ---------------------------------------------------------------------------------------------
-_KIND = {"alg2_plain_fwd": 0, "alg3_lazy_fwd": 1, "alg4_lazy_inv": 2, "plain_inv": 3}
+_KIND = {"alg2_plain_fwd": 0, "alg3_lazy_fwd": 1, "alg4_lazy_inv": 2, "plain_inv": 3, "alg5_mont_fwd": 4,
+         "mont_inv": 5}
 
 
 @pytest.mark.parametrize("kind", list(_KIND))
 @pytest.mark.parametrize("wb,p", [(32, P30), (32, 167772161), (64, P62)], ids=["p30", "p28", "p62"])
 def test_butterfly_theorems(ctx, kind, wb, p):
     """Each device butterfly against its algorithm's stated output range and congruences
-    (Theorems 1-3), with exact Python integers, on random and edge operands."""
+    (Theorems 1-4), with exact Python integers, on random and edge operands."""
     k = _KIND[kind]
     beta = 1 << wb
-    in_bound = {0: p, 1: 2 * p, 2: 4 * p, 3: p}[k]
-    out_bound = {0: p, 1: 2 * p, 2: 4 * p, 3: p}[k]
+    in_bound = {0: p, 1: 2 * p, 2: 4 * p, 3: p, 4: 2 * p, 5: 4 * p}[k]
+    out_bound = {0: p, 1: 2 * p, 2: 4 * p, 3: p, 4: 2 * p, 5: 4 * p}[k]
     r = random.Random(k * 7 + wb)
     g = G62 if wb == 64 else hntt.primitive_root(p)
     omega = pow(g, (p - 1) >> 10, p)
@@ -245,9 +264,14 @@ def test_butterfly_theorems(ctx, kind, wb, p):
         xs.append(r.randrange(in_bound))
         ys.append(r.randrange(in_bound))
         ws.append(r.randrange(1, p))
-    wps = [(W * beta) // p for W in ws]
+    if k >= 4:  # Algorithm 5 inputs: W' = W beta mod p and J = p^-1 mod beta
+        wargs = [(W * beta) % p for W in ws]
+        wps = [pow(p, -1, beta)] * len(ws)
+    else:
+        wargs = ws
+        wps = [(W * beta) // p for W in ws]
     dt = _np_dtype(wb)
-    X, Y, W, WP = (dev(np.array(v, dtype=dt)) for v in (xs, ys, ws, wps))
+    X, Y, W, WP = (dev(np.array(v, dtype=dt)) for v in (xs, ys, wargs, wps))
     XO, YO = torch.empty_like(X), torch.empty_like(Y)
     ctx.debug_butterfly(k, p, X, Y, W, WP, XO, YO)
     xo = host(XO, dt).tolist()
@@ -255,7 +279,7 @@ def test_butterfly_theorems(ctx, kind, wb, p):
     for i in range(len(xs)):
         a, b, w_ = xs[i], ys[i], ws[i]
         assert 0 <= xo[i] < out_bound and 0 <= yo[i] < out_bound, (kind, a, b, w_, xo[i], yo[i])
-        if k in (0, 1):
+        if k in (0, 1, 4):
             assert xo[i] % p == (a + b) % p and yo[i] % p == w_ * (a - b) % p, (kind, a, b, w_)
         else:
             assert xo[i] % p == (a + w_ * b) % p and yo[i] % p == (a - w_ * b) % p, (kind, a, b, w_)
@@ -277,8 +301,9 @@ def test_pointwise_mul(ctx, orc, wb, p):
     np.testing.assert_array_equal(host(ta, dt).astype(np.uint64), orc.pointwise(a, b, p))
 
 
+@pytest.mark.parametrize("policy", ["lazy", "mont"])
 @pytest.mark.parametrize("wb,l", [(32, 20), (32, 13), (64, 22), (64, 15)])
-def test_schedule_independence(ctx, orc, wb, l):
+def test_schedule_independence(ctx, orc, wb, l, policy):
     """Every legal schedule gives bit-identical results (a cross-schedule check that would
     expose LDS races or indexing mistakes tied to one tile shape)."""
     from paper_1205_2926_amd.autotune import candidates
@@ -293,12 +318,12 @@ def test_schedule_independence(ctx, orc, wb, l):
     for cand in cands[:: max(1, len(cands) // 10)]:
         ctx.set_tuning(l, wb, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
         t = dev(x)
-        ctx.ntt_forward(t, p, w)
+        ctx.ntt_forward(t, p, w, **_kw(policy))
         got = host(t, dt)
         if ref is None:
             ref = got
             np.testing.assert_array_equal(got[0].astype(np.uint64), orc.forward(x[0], l, p, w))
         np.testing.assert_array_equal(got, ref, err_msg=str(cand))
-        ctx.ntt_inverse(t, p, w)
+        ctx.ntt_inverse(t, p, w, **_kw(policy))
         np.testing.assert_array_equal(host(t, dt), x, err_msg=str(cand))
     ctx.set_tuning(l, wb)
