@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "libntt_oracle.so")
 
 _u64 = ctypes.c_uint64
 _p64 = ctypes.POINTER(ctypes.c_uint64)
+_p32 = ctypes.POINTER(ctypes.c_uint32)
 _lib = None
 
 
@@ -56,6 +57,8 @@ def _declare(lib):
         "oracle_schoolbook": (None, [_p64, ctypes.c_size_t, _p64, ctypes.c_size_t, _p64]),
         "oracle_product_coeff": (_u64, [_p64, ctypes.c_size_t, _p64, ctypes.c_size_t, ctypes.c_size_t]),
         "oracle_poly_eval": (_u64, [_p64, ctypes.c_size_t, _u64, _u64]),
+        "oracle_bigmul_schoolbook": (None, [_p32, ctypes.c_size_t, _p32, ctypes.c_size_t, _p32]),
+        "oracle_limbs_mod": (_u64, [_p32, ctypes.c_size_t, _u64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -79,6 +82,11 @@ def load(path: str | None = None, rebuild: bool = False):
 def _ptr(a: np.ndarray):
     assert a.dtype == np.uint64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_p64)
+
+
+def _ptr32(a: np.ndarray):
+    assert a.dtype == np.uint32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_p32)
 
 
 def _u64arr(x) -> np.ndarray:
@@ -183,3 +191,32 @@ class Oracle:
         a = _u64arr(a)
         b = _u64arr(b)
         return int(self.lib.oracle_product_coeff(_ptr(a), a.size, _ptr(b), b.size, k))
+
+    # large-integer products (Section 1: the application of fast transforms)
+    def bigmul_schoolbook(self, a, b) -> np.ndarray:
+        """a * b for little-endian base-2^32 limb arrays by long multiplication (O(na nb))."""
+        a = np.ascontiguousarray(a, dtype=np.uint32)
+        b = np.ascontiguousarray(b, dtype=np.uint32)
+        out = np.empty(a.size + b.size, dtype=np.uint32)
+        self.lib.oracle_bigmul_schoolbook(_ptr32(a), a.size, _ptr32(b), b.size, _ptr32(out))
+        return out
+
+    @staticmethod
+    def limbs_to_int(x) -> int:
+        return int.from_bytes(np.ascontiguousarray(x, dtype="<u4").tobytes(), "little")
+
+    @staticmethod
+    def int_to_limbs(v: int, n: int) -> np.ndarray:
+        return np.frombuffer(v.to_bytes(4 * n, "little"), dtype="<u4").astype(np.uint32)
+
+    def bigmul(self, a, b) -> np.ndarray:
+        """a * b as na + nb limbs, with Python's arbitrary-precision integer product as the
+        multiplication step (fast enough for the larger test cases)."""
+        a = np.ascontiguousarray(a, dtype=np.uint32)
+        b = np.ascontiguousarray(b, dtype=np.uint32)
+        return self.int_to_limbs(self.limbs_to_int(a) * self.limbs_to_int(b), a.size + b.size)
+
+    def limbs_mod(self, x, m: int) -> int:
+        """The integer with limbs x, reduced mod m."""
+        x = np.ascontiguousarray(x, dtype=np.uint32)
+        return int(self.lib.oracle_limbs_mod(_ptr32(x), x.size, m))

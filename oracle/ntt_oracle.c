@@ -19,6 +19,8 @@
  *   - the inverse as Algorithm 1 run backwards, giving the
  *     butterfly (X, Y) -> (X + W Y, X - W Y)                  (Section 4, first paragraph)
  *   - the problem setting: p prime, L = 2^l divides p - 1     (Section 1)
+ *   - large-integer multiplication, the application that
+ *     motivates fast transforms                               (Section 1, first paragraph)
  *
  * Parity pins for every function live in tests/oracle_pins.py; no
  * function here is "parity unpinned".
@@ -291,5 +293,31 @@ uint64_t oracle_product_coeff(const uint64_t *a, size_t na, const uint64_t *b, s
 uint64_t oracle_poly_eval(const uint64_t *c, size_t n, uint64_t r, uint64_t m) {
   uint64_t acc = 0;
   for (size_t i = n; i-- > 0;) acc = add_mod(mul_mod(acc, r % m, m), c[i] % m, m);
+  return acc;
+}
+
+/* Long multiplication of non-negative integers given as little-endian base-2^32
+ * limbs (the schoolbook method, with one carry pass per row): out[0..na+nb) =
+ * a * b.  Every partial sum out[i+j] + a_i b_j + carry is below 2^64, since
+ * (2^32 - 1)^2 + 2 (2^32 - 1) = 2^64 - 1.  Used to pin large-integer products. */
+void oracle_bigmul_schoolbook(const uint32_t *a, size_t na, const uint32_t *b, size_t nb, uint32_t *out) {
+  memset(out, 0, (na + nb) * sizeof(uint32_t));
+  for (size_t i = 0; i < na; ++i) {
+    uint64_t carry = 0;
+    for (size_t j = 0; j < nb; ++j) {
+      const uint64_t t = (uint64_t)a[i] * b[j] + out[i + j] + carry;
+      out[i + j] = (uint32_t)t;
+      carry = t >> 32;
+    }
+    out[i + nb] = (uint32_t)carry;
+  }
+}
+
+/* The integer given by n little-endian base-2^32 limbs, reduced mod m (Horner's
+ * rule from the most significant limb; m < 2^63). */
+uint64_t oracle_limbs_mod(const uint32_t *x, size_t n, uint64_t m) {
+  const uint64_t base = (uint64_t)(((u128)1 << 32) % m);
+  uint64_t acc = 0;
+  for (size_t i = n; i-- > 0;) acc = add_mod(mul_mod(acc, base, m), (uint64_t)x[i] % m, m);
   return acc;
 }

@@ -318,6 +318,32 @@ def pin_poly_eval(orc):
     assert orc.poly_eval(_conv(a, b), x, m) == orc.poly_eval(a, x, m) * orc.poly_eval(b, x, m) % m
 
 
+def pin_bigmul(orc):
+    """Long multiplication of limb arrays against Python's integer product (an independent
+    multiplication), the square of beta^n - 1 in closed form, and products by 0, 1 and beta^k."""
+    r = random.Random(26)
+    for na, nb in ((1, 1), (1, 7), (7, 1), (3, 3), (17, 40), (64, 5)):
+        a = np.array([r.randrange(1 << 32) for _ in range(na)], np.uint32)
+        b = np.array([r.randrange(1 << 32) for _ in range(nb)], np.uint32)
+        got = orc.bigmul_schoolbook(a, b)
+        want = orc.limbs_to_int(a) * orc.limbs_to_int(b)
+        assert orc.limbs_to_int(got) == want and got.size == na + nb
+        np.testing.assert_array_equal(orc.bigmul(a, b), got)
+    for n in (1, 2, 9):
+        # (beta^n - 1)^2 = beta^2n - 2 beta^n + 1: limbs 1, 0.., 0xFFFFFFFE, 0xFFFFFFFF..
+        ones = np.full(n, 0xFFFFFFFF, np.uint32)
+        want = np.array([1] + [0] * (n - 1) + [0xFFFFFFFE] + [0xFFFFFFFF] * (n - 1), np.uint32)
+        np.testing.assert_array_equal(orc.bigmul_schoolbook(ones, ones), want)
+    a = np.array([r.randrange(1 << 32) for _ in range(12)], np.uint32)
+    np.testing.assert_array_equal(orc.bigmul_schoolbook(a, np.zeros(3, np.uint32)), np.zeros(15, np.uint32))
+    np.testing.assert_array_equal(orc.bigmul_schoolbook(a, np.array([1], np.uint32))[:12], a)
+    shift = np.array([0, 0, 1], np.uint32)  # beta^2
+    np.testing.assert_array_equal(orc.bigmul_schoolbook(a, shift), np.concatenate([[0, 0], a, [0]]).astype(np.uint32))
+    for m in ((1 << 61) - 1, 998244353, 3):
+        assert orc.limbs_mod(a, m) == orc.limbs_to_int(a) % m
+
+
 ALL_PINS = [pin_golden_tiny, pin_forward_naive, pin_forward_sympy, pin_inverse_naive, pin_inverse_sympy,
             pin_roundtrip, pin_closed_forms, pin_dft_point, pin_bitrev, pin_number_theory, pin_prime_search,
-            pin_pointwise, pin_polymul_mod, pin_crt3, pin_schoolbook, pin_polymul_exact, pin_poly_eval]
+            pin_pointwise, pin_polymul_mod, pin_crt3, pin_schoolbook, pin_polymul_exact, pin_poly_eval,
+            pin_bigmul]

@@ -43,6 +43,11 @@ MUTANTS = [
     ("poly_eval_drops_coeff", "acc = add_mod(mul_mod(acc, r % m, m), c[i] % m, m);",
      "acc = mul_mod(acc, r % m, m);", 0),
     ("prime_search_step", "uint64_t c = k * step + 1;", "uint64_t c = k * step - 1;", 0),
+    ("bigmul_drops_carry", "const uint64_t t = (uint64_t)a[i] * b[j] + out[i + j] + carry;",
+     "const uint64_t t = (uint64_t)a[i] * b[j] + out[i + j];", 0),
+    ("bigmul_last_carry_slot", "out[i + nb] = (uint32_t)carry;", "out[i + nb - 1] += (uint32_t)carry;", 0),
+    ("limbs_mod_base", "acc = add_mod(mul_mod(acc, base, m), (uint64_t)x[i] % m, m);",
+     "acc = add_mod(acc, (uint64_t)x[i] % m, m);", 0),
 ]
 
 
