@@ -194,6 +194,35 @@ int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *plan, void *stre
 void hntt_polymul_plan_destroy(hntt_polymul_plan *plan);
 
 /* ---------------------------------------------------------------------------
+ * Large-integer multiplication (the application that Section 1 names for fast
+ * transforms): out = a * b for non-negative integers given as little-endian
+ * base-2^32 limbs.  The limbs are the coefficients of a polynomial product
+ * (hntt_polymul_*: three primes, lazy butterflies, Garner), whose exact
+ * coefficients (below min(na, nb) (2^32 - 1)^2 < 2^86 < q1 q2 q3) are carried
+ * into limbs on the device by a parallel carry scan.
+ *   a, b   na, nb limbs (device, 4-byte aligned), 1 <= na, nb and
+ *          2 * nextpow2(max(na, nb)) <= 2^23 (operands up to 2^22 limbs);
+ *   out    na + nb limbs (device, 4-byte aligned, not overlapping a or b);
+ *          the product always fits.
+ * flags: HNTT_PLAIN, HNTT_NO_GRAPH as for hntt_polymul_crt.  The plan form
+ * returns an hntt_polymul_plan, executed and destroyed with the
+ * hntt_polymul_plan_* calls above; hntt_bigmul_workspace_size gives its
+ * workspace from the lengths.  Errors: EINVAL (NULL/misaligned pointer, empty
+ * operand), EUNSUPPORTED (operand above 2^22 limbs), ENOMEM, EDEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const uint32_t *a;
+  const uint32_t *b;
+  uint32_t *out;
+  uint32_t na;
+  uint32_t nb;
+} hntt_bigmul_desc;
+int hntt_bigmul(hntt_ctx *ctx, const hntt_bigmul_desc *descs, size_t n, uint32_t flags, void *stream);
+int hntt_bigmul_plan_create(hntt_ctx *ctx, const hntt_bigmul_desc *descs, size_t n, uint32_t flags, void *workspace,
+                            size_t workspace_bytes, void *stream, hntt_polymul_plan **out);
+int hntt_bigmul_workspace_size(const hntt_bigmul_desc *descs, size_t n, size_t *bytes_out);
+
+/* ---------------------------------------------------------------------------
  * Host-side number theory (no device needed).  These are the parameters of
  * the problem setting in Section 1 and the Shoup constant of Algorithm 2.
  * ------------------------------------------------------------------------- */

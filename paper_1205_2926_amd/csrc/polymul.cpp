@@ -65,10 +65,12 @@ struct Sizing {
   std::vector<int> logs;
   std::vector<int> class_count;
   size_t ws_words = 0, chunks_ws = 0, chunks_out = 0;
-  size_t off_pairs = 0, off_cws = 0, off_cout = 0, off_xf = 0, total = 0;
+  size_t off_pairs = 0, off_cws = 0, off_cout = 0, off_xf = 0, off_state = 0, off_carry = 0, total = 0;
 };
 
-int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_ptrs, Sizing *sz) {
+// `big`: products of base-2^32 limb integers (na + nb uint32 limbs out) instead of
+// uint64 coefficient vectors (na + nb - 1 coefficients out).
+int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_ptrs, Sizing *sz, bool big = false) {
   sz->logs.assign(n, 0);
   sz->class_count.assign(kMaxPolyLog + 1, 0);
   for (size_t i = 0; i < n; ++i) {
@@ -77,7 +79,7 @@ int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_
     if (check_ptrs) {
       if (!d.a || !d.b || !d.out) return perr(ctx, HNTT_EINVAL, "product %zu: NULL pointer", i);
       if ((reinterpret_cast<uintptr_t>(d.a) | reinterpret_cast<uintptr_t>(d.b)) % 4 ||
-          reinterpret_cast<uintptr_t>(d.out) % 8)
+          reinterpret_cast<uintptr_t>(d.out) % (big ? 4 : 8))
         return perr(ctx, HNTT_EINVAL, "product %zu: misaligned pointer", i);
     }
     const int l = log2_padded(d.na, d.nb);
@@ -86,7 +88,7 @@ int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_
     sz->logs[i] = l;
     sz->ws_words += 6ull << l;
     sz->chunks_ws += ((1ull << l) + kChunkWords - 1) / kChunkWords;
-    sz->chunks_out += ((uint64_t)d.na + d.nb - 1 + kChunkWords - 1) / kChunkWords;
+    sz->chunks_out += ((uint64_t)d.na + d.nb - (big ? 0 : 1) + kChunkWords - 1) / kChunkWords;
     sz->class_count[l]++;
   }
   if (sz->chunks_ws > (1u << 30) || sz->chunks_out > (1u << 30))
@@ -97,7 +99,10 @@ int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_
   sz->off_cws = align_up(sz->off_pairs + n * sizeof(PolyPair), 256);
   sz->off_cout = align_up(sz->off_cws + sz->chunks_ws * sizeof(ChunkEntry), 256);
   sz->off_xf = align_up(sz->off_cout + sz->chunks_out * sizeof(ChunkEntry), 256);
-  sz->total = align_up(sz->off_xf + n_xf * sizeof(XformEntry), 256);
+  // large-integer mode: carry state and carry-in of every output chunk
+  sz->off_state = align_up(sz->off_xf + n_xf * sizeof(XformEntry), 256);
+  sz->off_carry = align_up(sz->off_state + (big ? sz->chunks_out * 4 : 0), 256);
+  sz->total = align_up(sz->off_carry + (big ? sz->chunks_out * 4 : 0), 256);
   return HNTT_OK;
 }
 
@@ -113,6 +118,7 @@ struct ClassWork {
 struct hntt_polymul_plan {
   hntt_ctx *ctx = nullptr;
   uint32_t flags = 0;
+  bool big = false;  // large-integer products (limbs out) instead of coefficient vectors
   size_t n = 0;
   char *arena = nullptr;
   size_t arena_bytes = 0;
@@ -206,16 +212,21 @@ static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s) {
   if ((e = launch_poly_pointwise(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly pointwise)");
   for (const ClassWork &cw : pl->classes)
     if ((rc = run_class(ctx, cw, true, pl->flags, s))) return rc;
-  if ((e = launch_poly_crt(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly crt)");
+  if (pl->big) {
+    if ((e = launch_big_crt(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(big crt)");
+    if ((e = launch_big_carry(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(big carry)");
+  } else if ((e = launch_poly_crt(pl->args, s)) != hipSuccess) {
+    return hip_err(ctx, e, "launch(poly crt)");
+  }
   return HNTT_OK;
 }
 
 }  // namespace hntt
 
-extern "C" {
-
-int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *workspace,
-                             size_t workspace_bytes, void *stream, hntt_polymul_plan **out) {
+// Plan a batch of products: coefficient vectors (big = false) or large-integer
+// limb products (big = true); descriptors are checked on the host first.
+static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, bool big,
+                       void *workspace, size_t workspace_bytes, void *stream, hntt_polymul_plan **out) {
   if (!ctx || !out) return HNTT_EINVAL;
   ctx->last_error.clear();
   *out = nullptr;
@@ -224,7 +235,7 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
   if (n > (1u << 24)) return perr(ctx, HNTT_EUNSUPPORTED, "too many products in one plan");
   // host checks first: nothing touches the device before every descriptor is valid
   Sizing sz;
-  int rc = size_batch(ctx, descs, n, true, &sz);
+  int rc = size_batch(ctx, descs, n, true, &sz, big);
   if (rc) return rc;
   const std::vector<int> &logs = sz.logs;
   const std::vector<int> &class_count = sz.class_count;
@@ -244,6 +255,7 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
   std::unique_ptr<hntt_polymul_plan> pl(new hntt_polymul_plan());
   pl->ctx = ctx;
   pl->flags = flags;
+  pl->big = big;
   pl->n = n;
   pl->descs.assign(descs, descs + n);
 
@@ -295,9 +307,10 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
   for (size_t i = 0; i < n; ++i) {
     const hntt_poly_desc &d = descs[i];
     const int l = logs[i];
-    hp[i] = PolyPair{d.a, d.b, d.out, d.na, d.nb, (uint32_t)l, 0, woff};
+    hp[i] = PolyPair{d.a, d.b, d.out, d.na, d.nb, (uint32_t)l, (uint32_t)co_i, woff};
     for (uint64_t s = 0; s < (1ull << l); s += kChunkWords) hcw[cw_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
-    for (uint64_t s = 0; s < (uint64_t)d.na + d.nb - 1; s += kChunkWords) hco[co_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
+    const uint64_t nout = (uint64_t)d.na + d.nb - (big ? 0 : 1);
+    for (uint64_t s = 0; s < nout; s += kChunkWords) hco[co_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
     woff += 6ull << l;
   }
   // transform tables per length class: forward over A_k and B_k, inverse over A_k
@@ -334,6 +347,9 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
   a.chunks_out = reinterpret_cast<const ChunkEntry *>(pl->arena + off_cout);
   a.nchunks_out = (int)chunks_out;
   a.workspace = ws_dev;
+  a.npairs = (int)n;
+  a.chunk_state = reinterpret_cast<uint32_t *>(pl->arena + sz.off_state);
+  a.chunk_carry = reinterpret_cast<uint32_t *>(pl->arena + sz.off_carry);
   for (int k = 0; k < 3; ++k) {
     const uint64_t q = kPrimes[k];
     const uint64_t r = (uint64_t)(((u128)1 << 64) % q);
@@ -343,6 +359,7 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
   const uint64_t c12 = powmod(q1 % q2, q2 - 2, q2), c13 = powmod(q1 % q3, q3 - 2, q3),
                  c23 = powmod(q2 % q3, q3 - 2, q3);
   a.crt = CrtConst{(uint32_t)c12, shoup32(c12, q2), (uint32_t)c13, shoup32(c13, q3), (uint32_t)c23, shoup32(c23, q3)};
+  a.q12 = q1 * q2;
 
   // upload the metadata in stream order (the copy is staged before this call returns)
   hipError_t e = hipMemcpyAsync(pl->arena + off_pairs, meta.data(), meta.size(), hipMemcpyHostToDevice,
@@ -353,6 +370,40 @@ int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t 
     return r;
   }
   *out = pl.release();
+  return HNTT_OK;
+}
+
+static std::vector<hntt_poly_desc> as_poly(const hntt_bigmul_desc *descs, size_t n) {
+  std::vector<hntt_poly_desc> v(n);
+  for (size_t i = 0; i < n; ++i) v[i] = hntt_poly_desc{descs[i].a, descs[i].b, (uint64_t *)descs[i].out, descs[i].na,
+                                                        descs[i].nb};
+  return v;
+}
+
+extern "C" {
+
+int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *workspace,
+                             size_t workspace_bytes, void *stream, hntt_polymul_plan **out) {
+  return plan_create(ctx, descs, n, flags, false, workspace, workspace_bytes, stream, out);
+}
+
+int hntt_bigmul_plan_create(hntt_ctx *ctx, const hntt_bigmul_desc *descs, size_t n, uint32_t flags, void *workspace,
+                            size_t workspace_bytes, void *stream, hntt_polymul_plan **out) {
+  if (ctx && n && !descs) {
+    ctx->last_error = "descs is NULL";
+    return HNTT_EINVAL;
+  }
+  const std::vector<hntt_poly_desc> pd = as_poly(descs, n);
+  return plan_create(ctx, pd.data(), n, flags, true, workspace, workspace_bytes, stream, out);
+}
+
+int hntt_bigmul_workspace_size(const hntt_bigmul_desc *descs, size_t n, size_t *bytes_out) {
+  if (!bytes_out || (n && !descs)) return HNTT_EINVAL;
+  const std::vector<hntt_poly_desc> pd = as_poly(descs, n);
+  Sizing sz;
+  int rc = size_batch(nullptr, pd.data(), n, false, &sz, true);
+  if (rc) return rc;
+  *bytes_out = n ? sz.total : 0;
   return HNTT_OK;
 }
 
@@ -417,14 +468,13 @@ void hntt_polymul_plan_destroy(hntt_polymul_plan *pl) {
   delete pl;
 }
 
-int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream) {
-  if (!ctx) return HNTT_EINVAL;
-  ctx->last_error.clear();
-  if (n == 0) return HNTT_OK;
-  if (!descs) return perr(ctx, HNTT_EINVAL, "descs is NULL");
-  // reuse the cached plan when the same products are requested again (e.g. a benchmark loop)
+}  // extern "C"
+
+// One-shot form shared by polynomial and large-integer products: reuse the cached
+// plan when the same products are requested again (e.g. a benchmark loop).
+static int one_shot(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, bool big, void *stream) {
   hntt_polymul_plan *pl = ctx->poly_cache;
-  const bool same = pl && pl->flags == flags && pl->n == n &&
+  const bool same = pl && pl->flags == flags && pl->big == big && pl->n == n &&
                     std::memcmp(pl->descs.data(), descs, n * sizeof(hntt_poly_desc)) == 0;
   if (!same) {
     if (pl) {
@@ -432,11 +482,30 @@ int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint3
       hntt_polymul_plan_destroy(pl);
       ctx->poly_cache = nullptr;
     }
-    int rc = hntt_polymul_plan_create(ctx, descs, n, flags, nullptr, 0, stream, &pl);
+    int rc = plan_create(ctx, descs, n, flags, big, nullptr, 0, stream, &pl);
     if (rc) return rc;
     ctx->poly_cache = pl;
   }
   return hntt_polymul_plan_execute(ctx, pl, stream);
+}
+
+extern "C" {
+
+int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (n == 0) return HNTT_OK;
+  if (!descs) return perr(ctx, HNTT_EINVAL, "descs is NULL");
+  return one_shot(ctx, descs, n, flags, false, stream);
+}
+
+int hntt_bigmul(hntt_ctx *ctx, const hntt_bigmul_desc *descs, size_t n, uint32_t flags, void *stream) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (n == 0) return HNTT_OK;
+  if (!descs) return perr(ctx, HNTT_EINVAL, "descs is NULL");
+  const std::vector<hntt_poly_desc> pd = as_poly(descs, n);
+  return one_shot(ctx, pd.data(), n, flags, true, stream);
 }
 
 }  // extern "C"

@@ -93,7 +93,176 @@ __global__ void __launch_bounds__(kThreads) k_poly_crt(PolyArgs args) {
       uint32_t t = mulc(subm(r3, reduce_u32(v1, P3.q, P3.one_p), P3.q), cc.c13, cc.c13p, P3.q);
       t = subm(t, reduce_u32(v2, P3.q, P3.one_p), P3.q);
       const uint32_t v3 = mulc(t, cc.c23, cc.c23p, P3.q);
-      pp.out[j] = (uint64_t)v1 + (uint64_t)P1.q * ((uint64_t)v2 + (uint64_t)P2.q * v3);
+      static_cast<uint64_t *>(pp.out)[j] = (uint64_t)v1 + (uint64_t)P1.q * ((uint64_t)v2 + (uint64_t)P2.q * v3);
+    }
+  }
+}
+
+// Garner as above, but the coefficient x = v1 + q1 v2 + q1 q2 v3 < 2^89 is kept
+// whole: its three 32-bit words go to B1[j], B2[j], B3[j] (free after the
+// pointwise product).  Exact for any 32-bit limbs: x <= min(na, nb) (2^32 - 1)^2
+// < 2^86 < q1 q2 q3 when min(na, nb) <= 2^22.
+__global__ void __launch_bounds__(kThreads) k_big_crt(PolyArgs args) {
+  const PrimeConst &P1 = args.primes[0], &P2 = args.primes[1], &P3 = args.primes[2];
+  const CrtConst cc = args.crt;
+  const uint64_t q12 = args.q12;
+  for (int c = blockIdx.x; c < args.nchunks_out; c += gridDim.x) {
+    const ChunkEntry ce = args.chunks_out[c];
+    const PolyPair pp = args.pairs[ce.pair];
+    const uint32_t L = 1u << pp.log2_len;
+    const uint32_t nout = pp.na + pp.nb - 1;
+    uint32_t *ws = args.workspace + pp.ws_off;
+    for (uint32_t j = ce.start + threadIdx.x; j < ce.start + kChunk && j < nout; j += kThreads) {
+      const uint32_t r1 = ws[j], r2 = ws[2 * (size_t)L + j], r3 = ws[4 * (size_t)L + j];
+      const uint32_t v1 = r1;
+      const uint32_t v2 = mulc(subm(r2, reduce_u32(v1, P2.q, P2.one_p), P2.q), cc.c12, cc.c12p, P2.q);
+      uint32_t t = mulc(subm(r3, reduce_u32(v1, P3.q, P3.one_p), P3.q), cc.c13, cc.c13p, P3.q);
+      t = subm(t, reduce_u32(v2, P3.q, P3.one_p), P3.q);
+      const uint32_t v3 = mulc(t, cc.c23, cc.c23p, P3.q);
+      // 128-bit sum: a = v1 + q1 v2 < 2^61; q12 v3 from the 32-bit halves of q12 (< 2^60)
+      const uint64_t a = (uint64_t)v1 + (uint64_t)P1.q * v2;
+      const uint64_t p0 = (uint64_t)(uint32_t)q12 * v3;
+      const uint64_t p1 = (q12 >> 32) * v3;
+      uint64_t lo = p0 + (p1 << 32);
+      uint64_t hi = (p1 >> 32) + (lo < p0 ? 1 : 0);
+      const uint64_t lo2 = lo + a;
+      hi += lo2 < lo ? 1 : 0;
+      ws[1 * (size_t)L + j] = (uint32_t)lo2;
+      ws[3 * (size_t)L + j] = (uint32_t)(lo2 >> 32);
+      ws[5 * (size_t)L + j] = (uint32_t)hi;
+    }
+  }
+}
+
+// Carry pass.  With the coefficient words w0, w1, w2 of c_j (c_j = w0 + w1 2^32 +
+// w2 2^64), the product is sum_k s_k 2^(32k) with s_k = w0[k] + w1[k-1] + w2[k-2]
+// < 3 2^32.  Write s_k = lo_k + 2^32 hi_k (hi_k <= 2) and t_k = lo_k + hi_(k-1)
+// <= 2^32 + 1; then limb k is (t_k + c_k) mod 2^32 with carry c_(k+1) =
+// (t_k + c_k) >> 32 in {0, 1} and c_0 = 0.  Each position is a carry state:
+// generate (t_k >= 2^32: carry out 1), propagate (t_k = 2^32 - 1: carry out =
+// carry in) or kill (carry out 0).  A run of positions composes to its rightmost
+// non-propagate state, so the carries are an associative scan: per chunk, then
+// per product over its chunks, then inside each chunk again.
+enum : uint32_t { kKill = 0, kGen = 1, kProp = 2 };
+
+constexpr int kPerThread = kChunk / kThreads;  // consecutive limbs per thread
+
+struct BigView {
+  const uint32_t *w0, *w1, *w2;
+  uint32_t nout, nlimb;
+  __device__ __forceinline__ uint64_t s(int64_t k) const {  // s_k (0 outside the product)
+    if (k < 0 || k >= (int64_t)nlimb) return 0;
+    uint64_t v = 0;
+    if (k < (int64_t)nout) v += w0[k];
+    if (k >= 1 && k - 1 < (int64_t)nout) v += w1[k - 1];
+    if (k >= 2 && k - 2 < (int64_t)nout) v += w2[k - 2];
+    return v;
+  }
+};
+
+__device__ __forceinline__ BigView big_view(const PolyArgs &args, const PolyPair &pp) {
+  const uint32_t L = 1u << pp.log2_len;
+  const uint32_t *ws = args.workspace + pp.ws_off;
+  return BigView{ws + (size_t)L, ws + 3 * (size_t)L, ws + 5 * (size_t)L, pp.na + pp.nb - 1, pp.na + pp.nb};
+}
+
+// t_k and the states of this thread's kPerThread limbs starting at k0.
+__device__ __forceinline__ void big_states(const BigView &v, int64_t k0, uint64_t *t, uint32_t *st) {
+  uint64_t prev = v.s(k0 - 1);
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const uint64_t cur = v.s(k0 + i);
+    t[i] = (cur & 0xFFFFFFFFull) + (prev >> 32);
+    st[i] = (k0 + i >= (int64_t)v.nlimb) ? kProp
+            : t[i] >= (1ull << 32)       ? kGen
+            : t[i] == 0xFFFFFFFFull      ? kProp
+                                         : kKill;
+    prev = cur;
+  }
+}
+
+__device__ __forceinline__ uint32_t fold(uint32_t left, uint32_t right) { return right == kProp ? left : right; }
+
+// Carry into each thread of a 256-thread workgroup given the states of the
+// threads (in order) and the carry `cin` into thread 0; also returns the
+// workgroup's composed state in *all.  Uses wave ballots: the carry into a lane
+// is set by the nearest lane below it whose state is not propagate.
+__device__ __forceinline__ uint32_t wg_carry_in(uint32_t state, uint32_t cin, uint32_t *lds, uint32_t *all) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t nonp = __ballot(state != kProp);
+  const uint64_t gen = __ballot(state == kGen);
+  if (lane == 0) lds[wave] = nonp ? (uint32_t)((gen >> (63 - __clzll(nonp))) & 1) : kProp;
+  __syncthreads();
+  uint32_t c = cin;
+  for (int w = 0; w < wave; ++w) c = fold(c, lds[w]);
+  uint32_t a = kProp;
+  for (int w = 0; w < kThreads / 64; ++w) a = fold(a, lds[w]);
+  const uint64_t below = nonp & ((1ull << lane) - 1);
+  if (below) c = (uint32_t)((gen >> (63 - __clzll(below))) & 1);
+  __syncthreads();  // lds is reused by the caller's next scan
+  *all = a;
+  return c;
+}
+
+__global__ void __launch_bounds__(kThreads) k_big_chunk_state(PolyArgs args) {
+  __shared__ uint32_t lds[kThreads / 64];
+  for (int c = blockIdx.x; c < args.nchunks_out; c += gridDim.x) {
+    const ChunkEntry ce = args.chunks_out[c];
+    const PolyPair pp = args.pairs[ce.pair];
+    const BigView v = big_view(args, pp);
+    uint64_t t[kPerThread];
+    uint32_t st[kPerThread];
+    big_states(v, (int64_t)ce.start + threadIdx.x * kPerThread, t, st);
+    uint32_t mine = kProp;
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) mine = fold(mine, st[i]);
+    uint32_t all;
+    (void)wg_carry_in(mine, 0, lds, &all);
+    if (threadIdx.x == 0) args.chunk_state[c] = all;
+  }
+}
+
+// One workgroup per product: the carry into each of its chunks.
+__global__ void __launch_bounds__(kThreads) k_big_chunk_carry(PolyArgs args) {
+  __shared__ uint32_t lds[kThreads / 64];
+  for (int i = blockIdx.x; i < args.npairs; i += gridDim.x) {
+    const PolyPair pp = args.pairs[i];
+    const uint32_t nchunks = (pp.na + pp.nb + kChunk - 1) / kChunk;
+    const uint32_t per = (nchunks + kThreads - 1) / kThreads;
+    const uint32_t c0 = pp.chunk0 + threadIdx.x * per;
+    const uint32_t c1 = min(pp.chunk0 + nchunks, c0 + per);
+    uint32_t mine = kProp;
+    for (uint32_t c = c0; c < c1; ++c) mine = fold(mine, args.chunk_state[c]);
+    uint32_t all;
+    uint32_t carry = wg_carry_in(mine, 0, lds, &all);
+    for (uint32_t c = c0; c < c1; ++c) {
+      args.chunk_carry[c] = carry;
+      carry = fold(carry, args.chunk_state[c]);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_big_apply(PolyArgs args) {
+  __shared__ uint32_t lds[kThreads / 64];
+  for (int c = blockIdx.x; c < args.nchunks_out; c += gridDim.x) {
+    const ChunkEntry ce = args.chunks_out[c];
+    const PolyPair pp = args.pairs[ce.pair];
+    const BigView v = big_view(args, pp);
+    const int64_t k0 = (int64_t)ce.start + threadIdx.x * kPerThread;
+    uint64_t t[kPerThread];
+    uint32_t st[kPerThread];
+    big_states(v, k0, t, st);
+    uint32_t mine = kProp;
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) mine = fold(mine, st[i]);
+    uint32_t all;
+    uint32_t carry = wg_carry_in(mine, args.chunk_carry[c], lds, &all);
+    uint32_t *out = static_cast<uint32_t *>(pp.out);
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      const uint64_t x = t[i] + carry;
+      if (k0 + i < (int64_t)v.nlimb) out[k0 + i] = (uint32_t)x;
+      carry = (uint32_t)(x >> 32);
     }
   }
 }
@@ -115,6 +284,19 @@ hipError_t launch_poly_pointwise(const PolyArgs &a, hipStream_t s) {
 }
 hipError_t launch_poly_crt(const PolyArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_poly_crt, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_big_crt(const PolyArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_big_crt, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_big_carry(const PolyArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_big_chunk_state, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_big_chunk_carry, dim3(grid_for(a.npairs)), dim3(kThreads), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_big_apply, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

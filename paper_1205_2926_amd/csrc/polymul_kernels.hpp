@@ -13,10 +13,10 @@ namespace hntt {
 struct PolyPair {
   const uint32_t *a;
   const uint32_t *b;
-  uint64_t *out;
+  void *out;           // uint64_t coefficients, or (large-integer mode) uint32_t limbs
   uint32_t na, nb;
   uint32_t log2_len;
-  uint32_t reserved;
+  uint32_t chunk0;     // large-integer mode: index of the product's first output chunk
   uint64_t ws_off;
 };
 
@@ -42,14 +42,26 @@ struct PolyArgs {
   const ChunkEntry *chunks_ws;   // chunks over the padded length L of every product
   int nchunks_ws;
   const ChunkEntry *chunks_out;  // chunks over the na + nb - 1 output coefficients
+                                 // (large-integer mode: over the na + nb limbs)
   int nchunks_out;
+  int npairs;
   uint32_t *workspace;
   PrimeConst primes[3];
   CrtConst crt;
+  // Large-integer mode (products of base-2^32 limb integers): q1 q2, and per
+  // output chunk its carry state (kill / generate / propagate) and carry-in.
+  uint64_t q12;
+  uint32_t *chunk_state;
+  uint32_t *chunk_carry;
 };
 
 hipError_t launch_poly_prep(const PolyArgs &a, hipStream_t s);
 hipError_t launch_poly_pointwise(const PolyArgs &a, hipStream_t s);
 hipError_t launch_poly_crt(const PolyArgs &a, hipStream_t s);
+// Large-integer mode: exact coefficients as three 32-bit words each (Garner,
+// written over the dead B_k arrays of the workspace), then the carry pass that
+// turns them into na + nb limbs at PolyPair::out.
+hipError_t launch_big_crt(const PolyArgs &a, hipStream_t s);
+hipError_t launch_big_carry(const PolyArgs &a, hipStream_t s);
 
 }  // namespace hntt

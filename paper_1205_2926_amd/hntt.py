@@ -60,6 +60,10 @@ class PolyDesc(ctypes.Structure):
     _fields_ = [("a", _c_vp), ("b", _c_vp), ("out", _c_vp), ("na", _c_u32), ("nb", _c_u32)]
 
 
+class BigmulDesc(ctypes.Structure):
+    _fields_ = [("a", _c_vp), ("b", _c_vp), ("out", _c_vp), ("na", _c_u32), ("nb", _c_u32)]
+
+
 #: every function include/hntt.h declares, with its ctypes signature
 SIGNATURES = {
     "hntt_create": (ctypes.c_int, [ctypes.POINTER(_c_vp), ctypes.c_int, ctypes.c_size_t]),
@@ -77,6 +81,11 @@ SIGNATURES = {
     "hntt_polymul_workspace_size": (ctypes.c_int, [ctypes.POINTER(PolyDesc), ctypes.c_size_t,
                                                    ctypes.POINTER(ctypes.c_size_t)]),
     "hntt_polymul_plan_destroy": (None, [_c_vp]),
+    "hntt_bigmul": (ctypes.c_int, [_c_vp, ctypes.POINTER(BigmulDesc), ctypes.c_size_t, _c_u32, _c_vp]),
+    "hntt_bigmul_plan_create": (ctypes.c_int, [_c_vp, ctypes.POINTER(BigmulDesc), ctypes.c_size_t, _c_u32, _c_vp,
+                                               ctypes.c_size_t, _c_vp, ctypes.POINTER(_c_vp)]),
+    "hntt_bigmul_workspace_size": (ctypes.c_int, [ctypes.POINTER(BigmulDesc), ctypes.c_size_t,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "hntt_is_prime": (ctypes.c_int, [_c_u64]),
     "hntt_primitive_root": (_c_u64, [_c_u64]),
     "hntt_root_of_unity": (ctypes.c_int, [_c_u64, _c_u32, ctypes.POINTER(_c_u64)]),
@@ -141,6 +150,18 @@ def shoup_constant(w: int, p: int, word_bits: int) -> int:
     return int(out.value)
 
 
+def bigmul_workspace_size(lengths: Sequence[tuple[int, int]]) -> int:
+    """Workspace bytes of a large-integer product plan for (na, nb) limb counts (host only)."""
+    arr = (BigmulDesc * len(lengths))()
+    for i, (na, nb) in enumerate(lengths):
+        arr[i] = BigmulDesc(None, None, None, na, nb)
+    out = ctypes.c_size_t(0)
+    rc = load().hntt_bigmul_workspace_size(arr, len(lengths), ctypes.byref(out))
+    if rc:
+        raise HnttError(rc, "bad bigmul lengths")
+    return int(out.value)
+
+
 def polymul_workspace_size(lengths: Sequence[tuple[int, int]]) -> int:
     """Workspace bytes of a polymul plan for products of (na, nb) coefficients (host only)."""
     arr = (PolyDesc * len(lengths))()
@@ -174,17 +195,18 @@ def _stream_handle(stream, device) -> int:
 class PolymulPlan:
     """A planned batch of products (hntt_polymul_plan_*); execute() enqueues it, destroy() frees it."""
 
-    def __init__(self, ctx, pairs, outs, plain, graph, workspace, stream):
+    def __init__(self, ctx, pairs, outs, plain, graph, workspace, stream, big=False):
         self.ctx = ctx
-        self.arr = ctx.poly_descs(pairs, outs)
+        self.arr = ctx.bigmul_descs(pairs, outs) if big else ctx.poly_descs(pairs, outs)
         self.keep = (list(pairs), list(outs), workspace)
         flags = (PLAIN if plain else 0) | (0 if graph else NO_GRAPH)
         h = _c_vp()
         dev = outs[0].device if outs else torch.device("cuda", ctx.device)
         ws_ptr = workspace.data_ptr() if workspace is not None else None
         ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
-        ctx._check(ctx.lib.hntt_polymul_plan_create(ctx.handle, self.arr, len(pairs), flags, ws_ptr, ws_bytes,
-                                                    _stream_handle(stream, dev), ctypes.byref(h)))
+        create = ctx.lib.hntt_bigmul_plan_create if big else ctx.lib.hntt_polymul_plan_create
+        ctx._check(create(ctx.handle, self.arr, len(pairs), flags, ws_ptr, ws_bytes, _stream_handle(stream, dev),
+                          ctypes.byref(h)))
         self.handle = h
         self.device = dev
 
@@ -314,6 +336,31 @@ class Context:
     def polymul_plan(self, pairs, outs, plain: bool = False, graph: bool = True, workspace: torch.Tensor = None,
                      stream=None) -> "PolymulPlan":
         return PolymulPlan(self, pairs, outs, plain, graph, workspace, stream)
+
+    # -- large-integer products --------------------------------------------------------------------
+    @staticmethod
+    def bigmul_descs(pairs: Sequence[tuple[torch.Tensor, torch.Tensor]], outs: Sequence[torch.Tensor]):
+        arr = (BigmulDesc * len(pairs))()
+        for i, ((a, b), o) in enumerate(zip(pairs, outs)):
+            if a.element_size() != 4 or b.element_size() != 4 or o.element_size() != 4:
+                raise TypeError("limbs must be 32-bit integer tensors")
+            if o.numel() < a.numel() + b.numel():
+                raise ValueError("output shorter than na + nb limbs")
+            arr[i] = BigmulDesc(a.data_ptr(), b.data_ptr(), o.data_ptr(), a.numel(), b.numel())
+        return arr
+
+    def bigmul(self, pairs: Sequence[tuple[torch.Tensor, torch.Tensor]], outs: Sequence[torch.Tensor],
+               plain: bool = False, graph: bool = True, stream=None):
+        """out[i] = a_i * b_i for integers given as little-endian base-2^32 limbs (int32 tensors)."""
+        arr = self.bigmul_descs(pairs, outs)
+        dev = outs[0].device if outs else torch.device("cuda", self.device)
+        flags = (PLAIN if plain else 0) | (0 if graph else NO_GRAPH)
+        self._check(self.lib.hntt_bigmul(self.handle, arr, len(pairs), flags, _stream_handle(stream, dev)))
+        return outs
+
+    def bigmul_plan(self, pairs, outs, plain: bool = False, graph: bool = True, workspace: torch.Tensor = None,
+                    stream=None) -> "PolymulPlan":
+        return PolymulPlan(self, pairs, outs, plain, graph, workspace, stream, big=True)
 
     # -- schedule tuning ---------------------------------------------------------------------------
     def set_tuning(self, log2_len: int, word_bits: int, g_cols: int = 0, g_rows: int = 0, batch_chunk: int = 0):

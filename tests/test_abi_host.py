@@ -229,3 +229,14 @@ def test_serving_workspace_bound_covers_library_size():
                         np.zeros(int(2 ** gen.uniform(0, 20)), np.uint32)) for i in range(k)]
         exact = hntt.polymul_workspace_size([(r.a.size, r.b.size) for r in reqs])
         assert exact <= sum(r.workspace_bound() for r in reqs) + _GROUP_SLACK
+
+
+def test_bigmul_sizing_checks():
+    """Large-integer plans: workspace from lengths alone, operand limits checked on the host."""
+    ws = hntt.bigmul_workspace_size([(1000, 3000), (1, 1)])
+    assert ws >= hntt.polymul_workspace_size([(1000, 3000), (1, 1)])
+    assert hntt.bigmul_workspace_size([(1 << 22, 1 << 22)]) > 0
+    with pytest.raises(hntt.HnttError):
+        hntt.bigmul_workspace_size([((1 << 22) + 1, 1)])
+    with pytest.raises(hntt.HnttError):
+        hntt.bigmul_workspace_size([(0, 4)])
