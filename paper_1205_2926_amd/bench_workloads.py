@@ -2,6 +2,7 @@
 
 single1k  one forward NTT of 1024 residues (latency, lazy and plain)
 u64       8 NTTs of length 2^22 over the 62-bit prime, forward + inverse, lazy vs plain vs Montgomery
+bigmul    16 products of 2^20-limb (32 Mbit) integers, three primes + device carry scan
 polymul   4096 products with log-uniform lengths 2^8..2^16, three primes + CRT, one graph launch
 serving   Poisson stream of products (lengths 2^10..2^20), rate swept up to saturation
 Each returns one JSON-able dict.  Inputs are the seeded synthetic workloads of
@@ -170,3 +171,45 @@ def serving(args):
             "saturation_probes": probes,
             "sweep": [{k: st[k] for k in ("offered_fraction", "offered_rate", "products_per_s", "p50_ms", "p99_ms",
                                           "mean_ms", "requests", "batches", "peak_bytes")} for st in sweep]}
+
+
+def bigmul(args):
+    """Large-integer products: 16 pairs of 2^20-limb (32 Mbit) integers, uniform limbs,
+    one plan replayed as a HIP graph; checked by residues modulo 61-bit primes and the low
+    limbs; Python's integer product timed beside it on a smaller sample."""
+    import time as _time
+    import oracle
+    orc = oracle.Oracle()
+    n, count = 1 << 20, 16
+    gen = np.random.Generator(np.random.PCG64(7))
+    pairs = [(gen.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32),
+              gen.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)) for _ in range(count)]
+    ctx = hntt.Context(0)
+    dpairs = [(torch.from_numpy(a.view(np.int32)).cuda(), torch.from_numpy(b.view(np.int32)).cuda()) for a, b in pairs]
+    outs = [torch.empty(2 * n, dtype=torch.int32, device="cuda") for _ in range(count)]
+    res = {}
+    for policy in ("lazy", "plain"):
+        plan = ctx.bigmul_plan(dpairs, outs, plain=policy == "plain")
+        plan.execute()
+        torch.cuda.synchronize()
+        ms = _events_ms(plan.execute, max(3, args.steps // 2))
+        res[policy] = {"ms_per_batch": ms, "products_per_s": count / (ms / 1e3)}
+        plan.destroy()
+    got = [o.cpu().numpy().view(np.uint32) for o in outs]
+    for i in (0, count - 1):
+        a, b = pairs[i]
+        for m in (2305843009213693951, 2305843009213693921):
+            assert orc.limbs_mod(got[i], m) == orc.limbs_mod(a, m) * orc.limbs_mod(b, m) % m, "bigmul mismatch"
+        assert np.array_equal(got[i][:1000], orc.bigmul(a[:1000], b[:1000])[:1000]), "bigmul low limbs"
+    ctx.close()
+    ns = 1 << 19
+    a, b = orc.limbs_to_int(pairs[0][0][:ns]), orc.limbs_to_int(pairs[0][1][:ns])
+    t0 = _time.perf_counter()
+    _ = a * b
+    cpu_s = _time.perf_counter() - t0
+    return {"metric": "large-integer products/s, 2^20-limb (32 Mbit) operands", "unit": "products/s",
+            "value": res["lazy"]["products_per_s"], "workload": "16 products of 2^20 x 2^20 base-2^32 limbs",
+            "lazy": res["lazy"], "plain": res["plain"],
+            "lazy_over_plain": res["plain"]["ms_per_batch"] / res["lazy"]["ms_per_batch"],
+            "cpu_python_int": {"seconds": cpu_s, "sample": "one product of 2^19 x 2^19 limbs (16 Mbit operands), "
+                               "CPython integer multiplication, 1 core"}}
