@@ -39,7 +39,8 @@ struct SlotParams {
   const void *tt;     // split-twiddle factors of the pass (null when it has none)
   uint64_t scale_w;   // kWhole inverse: L^-1 (Montgomery policy: L^-1 beta mod p)
   uint64_t scale_wp;  // and its Shoup constant (unused by the Montgomery policy)
-  uint64_t jinv;      // Montgomery policy: p^-1 mod beta
+  uint64_t jinv;      // p^-1 mod beta (Montgomery policy; fused pointwise product)
+  uint64_t r2;        // beta^2 mod p (fused pointwise product)
 };
 
 // Which pass of the transform a launch performs.
@@ -62,7 +63,9 @@ struct RoundSplit {
 inline RoundSplit pass_split(int n, int word_bits) {
   if (word_bits == 32) {
     if (n <= 6) return {0, 0, n};
-    if (n <= 11) return {(n + 1) / 2, 0, n / 2};
+    if (n <= 10) return {(n + 1) / 2, 0, n / 2};
+    // n = 11, 12: three rounds of at most 16 words per thread, so that a 2^n-word
+    // tile has enough threads to fill the CU that its LDS footprint allows
     return {4, 4, n - 8};
   }
   if (n <= 5) return {0, 0, n};
@@ -94,6 +97,12 @@ struct PassParams {
   uint64_t scale_w;   // kWhole inverse: L^-1 (Montgomery policy: L^-1 beta mod p)
   uint64_t scale_wp;  // and its Shoup constant
   uint64_t jinv;      // Montgomery policy: p^-1 mod beta
+  // Final forward pass only: when nonzero, every output word is multiplied by the
+  // word at the same position of the "partner" transform that starts pm_off words
+  // before this one, and the product (fully reduced) replaces the partner's word
+  // (this transform's own words are left stale).  Used by the polynomial product:
+  // B_k's last pass multiplies into A_k.
+  uint32_t pm_off;
   // Batched form: transforms listed in a device table, each with its prime's slot;
   // when `table` is set, p/tw/tt/scale above are ignored and slots[] is used.
   const XformEntry *table;

@@ -247,8 +247,16 @@ struct KernelArgs {
   int group;                  // G
   int normalize;              // reduce the final output to [0,p)
   int scale;                  // whole inverse: multiply by L^-1 (slot scale_w, scale_wp)
+  uint32_t pm_off;            // fused pointwise product into the partner transform (0: off)
   SlotParams slots[kMaxSlots];
 };
+
+// The fused pointwise product of a final forward pass: a b mod p for a, b in [0,p),
+// as two Montgomery products (a b beta^-1, then times beta^2 beta^-1), fully reduced.
+__device__ __forceinline__ T pmul_word(T a, T b, const Mod &m, T r2) {
+  const T u = csub<T>(mont_lazy<Wd>(a, b, m.p, m.j), m.p);
+  return csub<T>(mont_lazy<Wd>(u, r2, m.p, m.j), m.p);
+}
 
 // What happens to a word on its way in from HBM and out to HBM.  The split
 // twiddle of a two-pass transform is applied where the data enters the second
@@ -307,6 +315,8 @@ template <bool Cols, class EdgeT>
 struct GlobalIO {
   static constexpr bool kContig = !Cols;
   HNTT_GLOBAL T *base;
+  HNTT_GLOBAL T *pm;            // rows/whole forward: partner base of the fused product, or null
+  T r2;
   __amdgpu_buffer_rsrc_t rsrc;  // Cols: the transform as a buffer
   uint32_t off;
   uint32_t stride;
@@ -322,6 +332,13 @@ struct GlobalIO {
   }
   __device__ __forceinline__ void store2(int lp, int up, T x) const {
     x = edge.out(x, lp + up);
+    if constexpr (!Cols) {
+      if (pm) {
+        HNTT_GLOBAL T *q = pm + off + (uint32_t)(lp + up);
+        *q = pmul_word(x, *q, edge.m, r2);
+        return;
+      }
+    }
     if constexpr (Cols) {
       buf_store(rsrc, (off + (uint32_t)lp * stride) * (uint32_t)sizeof(T), (uint32_t)up * stride * (uint32_t)sizeof(T),
                 x);
@@ -341,6 +358,15 @@ struct GlobalIO {
     T *w = reinterpret_cast<T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) w[i] = edge.out(v[i], pos + i);
+    if (pm) {
+      HNTT_GLOBAL Vec16 *dst = reinterpret_cast<HNTT_GLOBAL Vec16 *>(pm + (off + (uint32_t)pos));
+      const Vec16 pa = *dst;
+      const T *pw = reinterpret_cast<const T *>(&pa);
+#pragma unroll
+      for (int i = 0; i < kVec; ++i) w[i] = pmul_word(w[i], pw[i], edge.m, r2);
+      *dst = q;
+      return;
+    }
     *reinterpret_cast<HNTT_GLOBAL Vec16 *>(base + (off + (uint32_t)pos)) = q;
   }
 };
@@ -448,6 +474,8 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     if constexpr (TT)
       edge.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt), nsub * kTTStride * kTw);
     gio.base = gbase;
+    gio.pm = a.pm_off ? gbase - a.pm_off : nullptr;
+    gio.r2 = (T)sp.r2;
     if constexpr (Cols) {
       const uint32_t col = (uint32_t)unit * G + g;
       gio.rsrc = make_rsrc((const void *)gbase, (uint32_t)(C * N * sizeof(T)));
@@ -499,7 +527,17 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
             T *wo = reinterpret_cast<T *>(&o);
 #pragma unroll
             for (int j = 0; j < kVec; ++j) wo[j] = edge.out(w[j], c + j);
-            *reinterpret_cast<HNTT_GLOBAL Vec16 *>(rows0 + (size_t)row * N + c) = o;
+            if (gio.pm) {  // fused pointwise product into the partner transform
+              HNTT_GLOBAL Vec16 *dst =
+                  reinterpret_cast<HNTT_GLOBAL Vec16 *>(gio.pm + (size_t)unit * G * N + (size_t)row * N + c);
+              const Vec16 pa = *dst;
+              const T *pw = reinterpret_cast<const T *>(&pa);
+#pragma unroll
+              for (int j = 0; j < kVec; ++j) wo[j] = pmul_word(wo[j], pw[j], m, gio.r2);
+              *dst = o;
+            } else {
+              *reinterpret_cast<HNTT_GLOBAL Vec16 *>(rows0 + (size_t)row * N + c) = o;
+            }
           }
         }
       } else {
@@ -561,7 +599,7 @@ hipError_t dispatch_n(int n, bool tt, const KernelArgs &a, int blocks, int threa
 #if HNTT_WORD == 32
     HNTT_CASE(9, 5, 0, 4)
     HNTT_CASE(10, 5, 0, 5)
-    HNTT_CASE(11, 6, 0, 5)
+    HNTT_CASE(11, 4, 4, 3)
 #else
     HNTT_CASE(9, 3, 3, 3)
     HNTT_CASE(10, 4, 3, 3)
@@ -609,10 +647,13 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   a.group = pp.group;
   a.normalize = pp.normalize ? 1 : 0;
   a.scale = (pp.kind == PassKind::kWhole && pp.inverse) ? 1 : 0;
+  // the fused product belongs to the final forward pass (rows or whole) only
+  if (pp.pm_off && (pp.inverse || pp.kind == PassKind::kCols || !pp.normalize)) return hipErrorInvalidValue;
+  a.pm_off = pp.pm_off;
   if (pp.table) {
     for (int i = 0; i < pp.nslots; ++i) a.slots[i] = pp.slots[i];
   } else {
-    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp, pp.jinv};
+    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp, pp.jinv, 0};
   }
   const int blocks = (int)total;
   using namespace HNTT_NS;

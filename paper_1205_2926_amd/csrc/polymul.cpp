@@ -108,8 +108,8 @@ int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_
 
 struct ClassWork {
   int l;
-  int nfwd, ninv;
-  const XformEntry *fwd, *inv;  // device tables inside the arena
+  int nfwd, ninv;               // nfwd: entries of each forward table
+  const XformEntry *fwd_a, *fwd_b, *inv;  // device tables inside the arena
   const Tables *tab[3];
 };
 
@@ -134,11 +134,16 @@ struct hntt_polymul_plan {
 
 namespace hntt {
 
-// Enqueue one direction of the transforms of a length class (device table of entries).
-static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t flags, hipStream_t s) {
+// Enqueue the transforms of a length class listed in a device table.  `which`:
+// 0 = forward of the A_k, 1 = forward of the B_k with the pointwise product fused
+// into their last pass (it multiplies into A_k, which starts L words earlier),
+// 2 = inverse of the A_k.
+static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t flags, hipStream_t s) {
   const Plan plan = effective_plan(ctx, cw.l, 32);
-  const XformEntry *table = inverse ? cw.inv : cw.fwd;
+  const bool inverse = which == 2;
+  const XformEntry *table = which == 0 ? cw.fwd_a : which == 1 ? cw.fwd_b : cw.inv;
   const int count = inverse ? cw.ninv : cw.nfwd;
+  const uint32_t pm_off = which == 1 ? (1u << cw.l) : 0u;
   if (count == 0) return HNTT_OK;
   PassParams base{};
   base.word_bits = 32;
@@ -155,6 +160,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t 
       sp.scale_w = t.linv;
       sp.scale_wp = t.linv_p;
       sp.jinv = t.jinv;
+      sp.r2 = (uint64_t)(((u128)1 << 64) % kPrimes[k]);
       sp.tt = nullptr;
       // the split twiddle enters with the second pass: rows (forward), columns (inverse)
       if (which == 0) sp.tw = inverse ? t.inv : t.fwd;               // whole
@@ -175,6 +181,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t 
     pp.log_other = 0;
     pp.group = 1;
     pp.normalize = true;
+    pp.pm_off = pm_off;
     slots_for(pp, 0);
     if ((e = launch_pass(pp, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly whole)");
     return HNTT_OK;
@@ -192,6 +199,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, bool inverse, uint32_t 
   slots_for(rows, 2);
   cols.normalize = inverse;
   rows.normalize = !inverse;
+  rows.pm_off = pm_off;
   if (!inverse) {
     if ((e = launch_pass(cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
     if ((e = launch_pass(rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
@@ -208,10 +216,11 @@ static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s) {
   int rc;
   if ((e = launch_poly_prep(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly prep)");
   for (const ClassWork &cw : pl->classes)
-    if ((rc = run_class(ctx, cw, false, pl->flags, s))) return rc;
-  if ((e = launch_poly_pointwise(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly pointwise)");
+    if ((rc = run_class(ctx, cw, 0, pl->flags, s))) return rc;
+  for (const ClassWork &cw : pl->classes)  // B_k transforms; their last pass multiplies into A_k
+    if ((rc = run_class(ctx, cw, 1, pl->flags, s))) return rc;
   for (const ClassWork &cw : pl->classes)
-    if ((rc = run_class(ctx, cw, true, pl->flags, s))) return rc;
+    if ((rc = run_class(ctx, cw, 2, pl->flags, s))) return rc;
   if (pl->big) {
     if ((e = launch_big_crt(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(big crt)");
     if ((e = launch_big_carry(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(big carry)");
@@ -313,21 +322,21 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
     for (uint64_t s = 0; s < nout; s += kChunkWords) hco[co_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
     woff += 6ull << l;
   }
-  // transform tables per length class: forward over A_k and B_k, inverse over A_k
+  // transform tables per length class: forward over A_k, forward over B_k, inverse over A_k
   size_t xi = 0;
   const XformEntry *dxf = reinterpret_cast<const XformEntry *>(pl->arena + off_xf);
   for (ClassWork &cw : classes) {
-    const size_t f0 = xi;
-    for (size_t i = 0; i < n; ++i) {
-      if (logs[i] != cw.l) continue;
-      const uint64_t L = 1ull << cw.l;
-      for (int k = 0; k < 3; ++k) {
-        hxf[xi++] = XformEntry{reinterpret_cast<uint64_t>(ws_dev + hp[i].ws_off + (2 * k) * L), (uint32_t)k, 0};
-        hxf[xi++] = XformEntry{reinterpret_cast<uint64_t>(ws_dev + hp[i].ws_off + (2 * k + 1) * L), (uint32_t)k, 0};
+    for (int half = 0; half < 2; ++half) {
+      const size_t f0 = xi;
+      for (size_t i = 0; i < n; ++i) {
+        if (logs[i] != cw.l) continue;
+        const uint64_t L = 1ull << cw.l;
+        for (int k = 0; k < 3; ++k)
+          hxf[xi++] = XformEntry{reinterpret_cast<uint64_t>(ws_dev + hp[i].ws_off + (2 * k + half) * L), (uint32_t)k, 0};
       }
+      (half ? cw.fwd_b : cw.fwd_a) = dxf + f0;
+      cw.nfwd = (int)(xi - f0);
     }
-    cw.fwd = dxf + f0;
-    cw.nfwd = (int)(xi - f0);
     const size_t i0 = xi;
     for (size_t i = 0; i < n; ++i) {
       if (logs[i] != cw.l) continue;

@@ -1,8 +1,9 @@
 // Kernels of the three-prime polynomial product (the application named in
-// Section 1 of the paper): operand preparation, the pointwise product of the
-// transforms, and Chinese remaindering of the three residue vectors (Garner).
-// All three are persistent: a fixed grid of workgroups strides over a table of
-// 1024-word chunks covering every product of the batch.
+// Section 1 of the paper): operand preparation and Chinese remaindering of the
+// three residue vectors (Garner), plus the carry pass of large-integer
+// products.  (The pointwise product of the transforms is fused into the last
+// forward pass of the B_k.)  All are persistent: a fixed grid of workgroups
+// strides over a table of 1024-word chunks covering every product of the batch.
 #include "modarith.hpp"
 #include "polymul_kernels.hpp"
 
@@ -28,15 +29,6 @@ __device__ __forceinline__ uint32_t subm(uint32_t a, uint32_t b, uint32_t q) {
   return dq < d ? dq : d;  // a >= b: d < q <= dq (no wrap) ; a < b: d wraps, dq = a - b + q < q
 }
 
-// Montgomery product a b 2^-32 mod q in [0, 2q) for a, b < 2q, q < 2^30 (the form of Algorithm 5).
-__device__ __forceinline__ uint32_t mont(uint32_t a, uint32_t b, uint32_t q, uint32_t j) {
-  const uint32_t r1 = __umulhi(a, b);
-  const uint32_t r0 = a * b;
-  const uint32_t m = r0 * j;
-  const uint32_t h = __umulhi(m, q);
-  return r1 - h + q;
-}
-
 __global__ void __launch_bounds__(kThreads) k_poly_prep(PolyArgs args) {
   for (int c = blockIdx.x; c < args.nchunks_ws; c += gridDim.x) {
     const ChunkEntry ce = args.chunks_ws[c];
@@ -51,25 +43,6 @@ __global__ void __launch_bounds__(kThreads) k_poly_prep(PolyArgs args) {
         const PrimeConst &pc = args.primes[k];
         ws[(2 * k) * (size_t)L + j] = reduce_u32(av, pc.q, pc.one_p);
         ws[(2 * k + 1) * (size_t)L + j] = reduce_u32(bv, pc.q, pc.one_p);
-      }
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kThreads) k_poly_pointwise(PolyArgs args) {
-  for (int c = blockIdx.x; c < args.nchunks_ws; c += gridDim.x) {
-    const ChunkEntry ce = args.chunks_ws[c];
-    const PolyPair pp = args.pairs[ce.pair];
-    const uint32_t L = 1u << pp.log2_len;
-    uint32_t *ws = args.workspace + pp.ws_off;
-    for (uint32_t j = ce.start + threadIdx.x; j < ce.start + kChunk && j < L; j += kThreads) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const PrimeConst &pc = args.primes[k];
-        uint32_t *A = ws + (2 * k) * (size_t)L;
-        const uint32_t *B = ws + (2 * k + 1) * (size_t)L;
-        uint32_t u = csub<uint32_t>(mont(A[j], B[j], pc.q, pc.jinv), pc.q);  // a b 2^-32
-        A[j] = csub<uint32_t>(mont(u, pc.r2, pc.q, pc.jinv), pc.q);          // times 2^64 2^-32
       }
     }
   }
@@ -99,8 +72,8 @@ __global__ void __launch_bounds__(kThreads) k_poly_crt(PolyArgs args) {
 }
 
 // Garner as above, but the coefficient x = v1 + q1 v2 + q1 q2 v3 < 2^89 is kept
-// whole: its three 32-bit words go to B1[j], B2[j], B3[j] (free after the
-// pointwise product).  Exact for any 32-bit limbs: x <= min(na, nb) (2^32 - 1)^2
+// whole: its three 32-bit words go to B1[j], B2[j], B3[j] (free once the B_k
+// transforms have multiplied into the A_k).  Exact for any 32-bit limbs: x <= min(na, nb) (2^32 - 1)^2
 // < 2^86 < q1 q2 q3 when min(na, nb) <= 2^22.
 __global__ void __launch_bounds__(kThreads) k_big_crt(PolyArgs args) {
   const PrimeConst &P1 = args.primes[0], &P2 = args.primes[1], &P3 = args.primes[2];
@@ -276,10 +249,6 @@ int grid_for(int chunks) {
 
 hipError_t launch_poly_prep(const PolyArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_poly_prep, dim3(grid_for(a.nchunks_ws)), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_poly_pointwise(const PolyArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_poly_pointwise, dim3(grid_for(a.nchunks_ws)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_poly_crt(const PolyArgs &a, hipStream_t s) {

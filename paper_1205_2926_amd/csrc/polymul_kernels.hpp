@@ -26,8 +26,8 @@ struct ChunkEntry {
   uint32_t start;
 };
 
-// Per-prime constants: q, floor(2^32/q) (Shoup constant of 1), q^-1 mod 2^32
-// (Montgomery), 2^64 mod q.
+// Per-prime constants: q, floor(2^32/q) (Shoup constant of 1), q^-1 mod 2^32,
+// 2^64 mod q.
 struct PrimeConst {
   uint32_t q, one_p, jinv, r2;
 };
@@ -56,7 +56,6 @@ struct PolyArgs {
 };
 
 hipError_t launch_poly_prep(const PolyArgs &a, hipStream_t s);
-hipError_t launch_poly_pointwise(const PolyArgs &a, hipStream_t s);
 hipError_t launch_poly_crt(const PolyArgs &a, hipStream_t s);
 // Large-integer mode: exact coefficients as three 32-bit words each (Garner,
 // written over the dead B_k arrays of the workspace), then the carry pass that
