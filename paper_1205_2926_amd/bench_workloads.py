@@ -3,6 +3,8 @@
 single1k  one forward NTT of 1024 residues (latency, lazy and plain)
 u64       8 NTTs of length 2^22 over the 62-bit prime, forward + inverse, lazy vs plain vs Montgomery
 bigmul    16 products of 2^20-limb (32 Mbit) integers, three primes + device carry scan
+table1    host CPU: Algorithm 2 vs Algorithm 3, one transform of 2^11 over the 62-bit prime
+          (the design of the paper's Table 1), time per butterfly on one core
 polymul   4096 products with log-uniform lengths 2^8..2^16, three primes + CRT, one graph launch
 serving   Poisson stream of products (lengths 2^10..2^20), rate swept up to saturation
 Each returns one JSON-able dict.  Inputs are the seeded synthetic workloads of
@@ -213,3 +215,17 @@ def bigmul(args):
             "lazy_over_plain": res["plain"]["ms_per_batch"] / res["lazy"]["ms_per_batch"],
             "cpu_python_int": {"seconds": cpu_s, "sample": "one product of 2^19 x 2^19 limbs (16 Mbit operands), "
                                "CPython integer multiplication, 1 core"}}
+
+
+def table1(args):
+    """Same-host counterpart of Table 1 (no GPU): one-core transforms of length 2^11 over the
+    62-bit prime with Algorithm 2 and Algorithm 3 butterflies, time per butterfly."""
+    from . import cpu
+    from .workloads import G62, P62, uniform_residues
+    w = hntt.root_of_unity(P62, 11)
+    x = uniform_residues(8, 1 << 11, P62, np.uint64)
+    r = cpu.run(x, P62, w, reps=20000)
+    return {"metric": "ns per butterfly, one CPU core, L = 2^11, 62-bit p (Table 1 design)", "unit": "ns",
+            "value": r["alg3"]["ns_per_butterfly"], **r,
+            "paper_table1_cycles": {"Westmere": {"alg2": 10.1, "alg3": 6.9}, "Sandy Bridge": {"alg2": 9.1, "alg3": 5.9},
+                                    "Piledriver": {"alg2": 13.9, "alg3": 12.0}}}
