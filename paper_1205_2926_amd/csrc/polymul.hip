@@ -75,36 +75,30 @@ __global__ void __launch_bounds__(kThreads) k_poly_crt(PolyArgs args) {
 // whole: its three 32-bit words go to B1[j], B2[j], B3[j] (free once the B_k
 // transforms have multiplied into the A_k).  Exact for any 32-bit limbs: x <= min(na, nb) (2^32 - 1)^2
 // < 2^86 < q1 q2 q3 when min(na, nb) <= 2^22.
-__global__ void __launch_bounds__(kThreads) k_big_crt(PolyArgs args) {
+// The three 32-bit words of coefficient j of a product (its residues are at ws[j],
+// ws[2L + j], ws[4L + j]).
+__device__ __forceinline__ void garner_words(const PolyArgs &args, const uint32_t *ws, uint32_t L, uint32_t j,
+                                             uint32_t &w0, uint32_t &w1, uint32_t &w2) {
   const PrimeConst &P1 = args.primes[0], &P2 = args.primes[1], &P3 = args.primes[2];
-  const CrtConst cc = args.crt;
+  const CrtConst &cc = args.crt;
+  const uint32_t r1 = ws[j], r2 = ws[2 * (size_t)L + j], r3 = ws[4 * (size_t)L + j];
+  const uint32_t v1 = r1;
+  const uint32_t v2 = mulc(subm(r2, reduce_u32(v1, P2.q, P2.one_p), P2.q), cc.c12, cc.c12p, P2.q);
+  uint32_t t = mulc(subm(r3, reduce_u32(v1, P3.q, P3.one_p), P3.q), cc.c13, cc.c13p, P3.q);
+  t = subm(t, reduce_u32(v2, P3.q, P3.one_p), P3.q);
+  const uint32_t v3 = mulc(t, cc.c23, cc.c23p, P3.q);
+  // 128-bit sum: a = v1 + q1 v2 < 2^61; q12 v3 from the 32-bit halves of q12 (< 2^60)
   const uint64_t q12 = args.q12;
-  for (int c = blockIdx.x; c < args.nchunks_out; c += gridDim.x) {
-    const ChunkEntry ce = args.chunks_out[c];
-    const PolyPair pp = args.pairs[ce.pair];
-    const uint32_t L = 1u << pp.log2_len;
-    const uint32_t nout = pp.na + pp.nb - 1;
-    uint32_t *ws = args.workspace + pp.ws_off;
-    for (uint32_t j = ce.start + threadIdx.x; j < ce.start + kChunk && j < nout; j += kThreads) {
-      const uint32_t r1 = ws[j], r2 = ws[2 * (size_t)L + j], r3 = ws[4 * (size_t)L + j];
-      const uint32_t v1 = r1;
-      const uint32_t v2 = mulc(subm(r2, reduce_u32(v1, P2.q, P2.one_p), P2.q), cc.c12, cc.c12p, P2.q);
-      uint32_t t = mulc(subm(r3, reduce_u32(v1, P3.q, P3.one_p), P3.q), cc.c13, cc.c13p, P3.q);
-      t = subm(t, reduce_u32(v2, P3.q, P3.one_p), P3.q);
-      const uint32_t v3 = mulc(t, cc.c23, cc.c23p, P3.q);
-      // 128-bit sum: a = v1 + q1 v2 < 2^61; q12 v3 from the 32-bit halves of q12 (< 2^60)
-      const uint64_t a = (uint64_t)v1 + (uint64_t)P1.q * v2;
-      const uint64_t p0 = (uint64_t)(uint32_t)q12 * v3;
-      const uint64_t p1 = (q12 >> 32) * v3;
-      uint64_t lo = p0 + (p1 << 32);
-      uint64_t hi = (p1 >> 32) + (lo < p0 ? 1 : 0);
-      const uint64_t lo2 = lo + a;
-      hi += lo2 < lo ? 1 : 0;
-      ws[1 * (size_t)L + j] = (uint32_t)lo2;
-      ws[3 * (size_t)L + j] = (uint32_t)(lo2 >> 32);
-      ws[5 * (size_t)L + j] = (uint32_t)hi;
-    }
-  }
+  const uint64_t a = (uint64_t)v1 + (uint64_t)P1.q * v2;
+  const uint64_t p0 = (uint64_t)(uint32_t)q12 * v3;
+  const uint64_t p1 = (q12 >> 32) * v3;
+  const uint64_t lo = p0 + (p1 << 32);
+  uint64_t hi = (p1 >> 32) + (lo < p0 ? 1 : 0);
+  const uint64_t lo2 = lo + a;
+  hi += lo2 < lo ? 1 : 0;
+  w0 = (uint32_t)lo2;
+  w1 = (uint32_t)(lo2 >> 32);
+  w2 = (uint32_t)hi;
 }
 
 // Carry pass.  With the coefficient words w0, w1, w2 of c_j (c_j = w0 + w1 2^32 +
@@ -177,20 +171,58 @@ __device__ __forceinline__ uint32_t wg_carry_in(uint32_t state, uint32_t cin, ui
   return c;
 }
 
-__global__ void __launch_bounds__(kThreads) k_big_chunk_state(PolyArgs args) {
+// Garner for the coefficients of one 1024-limb chunk, written to B1, B2, B3 as
+// above, and, from the same words kept in LDS (plus the three coefficients before
+// the chunk, recomputed), the chunk's composed carry state.
+__global__ void __launch_bounds__(kThreads) k_big_crt_state(PolyArgs args) {
+  constexpr int kHalo = 3;  // s_(k-1) for the chunk's first limb needs coefficient start - 3
+  __shared__ uint32_t W[3][kChunk + kHalo];
   __shared__ uint32_t lds[kThreads / 64];
   for (int c = blockIdx.x; c < args.nchunks_out; c += gridDim.x) {
     const ChunkEntry ce = args.chunks_out[c];
     const PolyPair pp = args.pairs[ce.pair];
-    const BigView v = big_view(args, pp);
-    uint64_t t[kPerThread];
-    uint32_t st[kPerThread];
-    big_states(v, (int64_t)ce.start + threadIdx.x * kPerThread, t, st);
+    const uint32_t L = 1u << pp.log2_len;
+    const uint32_t nout = pp.na + pp.nb - 1, nlimb = pp.na + pp.nb;
+    uint32_t *ws = args.workspace + pp.ws_off;
+    const int64_t j0 = (int64_t)ce.start - kHalo;  // coefficient of LDS entry 0
+    for (int i = threadIdx.x; i < kChunk + kHalo; i += kThreads) {
+      const int64_t j = j0 + i;
+      uint32_t w0 = 0, w1 = 0, w2 = 0;
+      if (j >= 0 && j < (int64_t)nout) {
+        garner_words(args, ws, L, (uint32_t)j, w0, w1, w2);
+        if (i >= kHalo) {  // this chunk's own coefficients
+          ws[1 * (size_t)L + j] = w0;
+          ws[3 * (size_t)L + j] = w1;
+          ws[5 * (size_t)L + j] = w2;
+        }
+      }
+      W[0][i] = w0;
+      W[1][i] = w1;
+      W[2][i] = w2;
+    }
+    __syncthreads();
+    // s_k = w0[k] + w1[k-1] + w2[k-2] from LDS (zero outside the product)
+    auto s_at = [&](int64_t k) -> uint64_t {
+      if (k < 0 || k >= (int64_t)nlimb) return 0;
+      const int i = (int)(k - j0);
+      return (uint64_t)W[0][i] + W[1][i - 1] + W[2][i - 2];
+    };
+    const int64_t k0 = (int64_t)ce.start + threadIdx.x * kPerThread;
+    uint64_t prev = s_at(k0 - 1);
     uint32_t mine = kProp;
 #pragma unroll
-    for (int i = 0; i < kPerThread; ++i) mine = fold(mine, st[i]);
+    for (int i = 0; i < kPerThread; ++i) {
+      const uint64_t cur = s_at(k0 + i);
+      const uint64_t t = (cur & 0xFFFFFFFFull) + (prev >> 32);
+      const uint32_t st = (k0 + i >= (int64_t)nlimb) ? kProp
+                          : t >= (1ull << 32)          ? kGen
+                          : t == 0xFFFFFFFFull         ? kProp
+                                                       : kKill;
+      mine = fold(mine, st);
+      prev = cur;
+    }
     uint32_t all;
-    (void)wg_carry_in(mine, 0, lds, &all);
+    (void)wg_carry_in(mine, 0, lds, &all);  // ends with a barrier: W may be reused
     if (threadIdx.x == 0) args.chunk_state[c] = all;
   }
 }
@@ -256,13 +288,11 @@ hipError_t launch_poly_crt(const PolyArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_big_crt(const PolyArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_big_crt, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_big_crt_state, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_big_carry(const PolyArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_big_chunk_state, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
   hipLaunchKernelGGL(k_big_chunk_carry, dim3(grid_for(a.npairs)), dim3(kThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_big_apply, dim3(grid_for(a.nchunks_out)), dim3(kThreads), 0, s, a);
