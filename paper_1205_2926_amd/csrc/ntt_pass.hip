@@ -1,26 +1,33 @@
 // One NTT pass kernel family, compiled once per (word size, direction):
-// HNTT_WORD = 32 | 64, HNTT_INVERSE = 0 | 1.
+// HNTT_WORD = 32 | 64, HNTT_INVERSE = 0 | 1, and templated on the butterfly
+// policy (Algorithm 2, Algorithms 3/4, or Algorithm 5 and its inverse), the pass
+// kind and the register rounds.
 //
-// A workgroup owns G sub-transforms of length N = 2^n (n = KH + KL):
+// A workgroup owns G sub-transforms of length N = 2^n (n = KH + KM + KL):
 //   rows  G contiguous rows of a transform viewed as (#rows x N)   (also whole
 //         transforms: one row, #rows = 1)
 //   cols  G adjacent columns of a transform viewed as (N x #cols), row-major.
-// The n radix-2 stages of Algorithm 1 (Section 1) run in two register rounds:
-// the "high" round pairs position bits [KL, n) and the "low" round bits
-// [0, KL).  A thread keeps the 2^K elements of one group in registers for all
-// K stages of a round, so the tile crosses LDS once per pass:
-//   forward (DIF):  HBM -> high round -> LDS -> low round -> HBM
-//   inverse (DIT):  HBM -> low round  -> LDS -> high round -> HBM
-// With KH = 0 there is one round and no LDS tile at all.  Global loads and
-// stores are issued directly by the rounds that touch HBM; lanes are laid out
-// so that each memory instruction covers contiguous words (columns fastest in
-// a cols pass, positions fastest in a rows pass).
+// The n radix-2 stages of Algorithm 1 (Section 1) run in up to three register
+// rounds: the "high" round pairs position bits [KM + KL, n), the middle round
+// bits [KL, KL + KM) and the "low" round bits [0, KL).  A thread keeps the 2^K
+// elements of one group in registers for all K stages of a round, and the tile
+// crosses LDS between rounds:
+//   forward (DIF):  HBM -> high -> LDS -> (middle -> LDS ->) low -> HBM
+//   inverse (DIT):  HBM -> low -> LDS -> (middle -> LDS ->) high -> HBM
+// With KH = 0 there is one round and no LDS tile.  Global loads and stores are
+// issued directly by the rounds that touch HBM; lanes are laid out so that each
+// memory instruction covers contiguous words (columns fastest in a cols pass,
+// positions fastest in a rows pass), and the forward row pass writes its output
+// through LDS so that consecutive lanes store consecutive 16 bytes.
 //
-// Twiddles of the high round depend on the thread's low position bits and are
-// read from an LDS copy of the table; twiddles of the low round are uniform
-// across the workgroup (their indices are compile-time multiples of
+// Twiddles of the high and middle rounds depend on the thread's low position
+// bits and are read from an LDS copy of the table; twiddles of the low round
+// are uniform across the workgroup (their indices are compile-time multiples of
 // 2^(n-1-b)), so they come straight from global memory through scalar loads,
-// and the butterflies whose twiddle is 1 skip the product entirely.
+// and the butterflies whose twiddle is 1 skip the product entirely.  The split
+// twiddle of a two-pass transform is applied where the data enters the second
+// pass (Edge), and the final forward pass of a polynomial product can multiply
+// its output into a partner transform (the pointwise product, GlobalIO::pm).
 #include "modarith.hpp"
 #include "ntt_kernels.hpp"
 
