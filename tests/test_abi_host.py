@@ -240,3 +240,30 @@ def test_bigmul_sizing_checks():
         hntt.bigmul_workspace_size([((1 << 22) + 1, 1)])
     with pytest.raises(hntt.HnttError):
         hntt.bigmul_workspace_size([(0, 4)])
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """There is no CPU fallback: loading a library that is not there raises HnttNotBuilt."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1205_2926_amd import hntt\n"
+            "try:\n"
+            "    hntt.load(%r)\n"
+            "except hntt.HnttNotBuilt:\n"
+            "    print('raised')\n") % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                        str(tmp_path / "libhntt.so"))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.stdout.strip() == "raised", out.stderr
+
+
+def test_oracle_is_not_imported_by_the_library():
+    """The product path never imports the oracle package."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1205_2926_amd.hntt, paper_1205_2926_amd.serve, paper_1205_2926_amd.autotune\n"
+            "print('oracle' in sys.modules)\n") % root
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.stdout.strip() == "False", out.stderr
