@@ -83,7 +83,7 @@ T inv_mod_pow2(T p) {  // p^-1 mod 2^bits for odd p, by Newton iteration
 }  // namespace
 
 size_t pass_lds_bytes(const PassParams &pp) {
-  if (pass_split(pp.n, pp.word_bits).kh == 0) return 0;
+  if (pass_split(pp.n, pp.word_bits, pp.kind == PassKind::kWhole).kh == 0) return 0;
   const size_t wb = pp.word_bits / 8;
   const size_t N = (size_t)1 << pp.n;
   // per-stage twiddle table (N pairs) + padded tile (see LdsIO in ntt_pass.hip)

@@ -60,8 +60,13 @@ constexpr int kMaxPassThreads = 512; // workgroup size limit of the pass kernels
 struct RoundSplit {
   int kh, km, kl;
 };
-inline RoundSplit pass_split(int n, int word_bits) {
+// `whole`: a one-pass transform, one per workgroup; 2^9 and 2^10 u32 words then
+// use three rounds so that the transform has a full wave of 64 threads (two
+// rounds would give it 32, half of every wave idle).
+inline RoundSplit pass_split(int n, int word_bits, bool whole = false) {
   if (word_bits == 32) {
+    if (whole && n == 9) return {3, 3, 3};
+    if (whole && n == 10) return {4, 3, 3};
     if (n <= 6) return {0, 0, n};
     if (n <= 10) return {(n + 1) / 2, 0, n / 2};
     // n = 11, 12: three rounds of at most 16 words per thread, so that a 2^n-word
@@ -75,8 +80,8 @@ inline RoundSplit pass_split(int n, int word_bits) {
   return {4, 4, n - 8};
 }
 // Threads per sub-transform: one group of the largest round each.
-inline int pass_tpt(int n, int word_bits) {
-  const RoundSplit r = pass_split(n, word_bits);
+inline int pass_tpt(int n, int word_bits, bool whole = false) {
+  const RoundSplit r = pass_split(n, word_bits, whole);
   const int kmax = r.kh > r.kl ? (r.kh > r.km ? r.kh : r.km) : (r.kl > r.km ? r.kl : r.km);
   return 1 << (n - kmax);
 }

@@ -587,9 +587,23 @@ hipError_t launch_tt(bool tt, const KernelArgs &a, int blocks, int threads, size
 
 // Round splits per word size; must agree with pass_split().
 template <int Pol, bool Cols>
-hipError_t dispatch_n(int n, bool tt, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t s) {
+hipError_t dispatch_n(int n, bool whole, bool tt, const KernelArgs &a, int blocks, int threads, size_t lds,
+                      hipStream_t s) {
 #define HNTT_CASE(N, KH, KM, KL) \
   case N: return launch_tt<Pol, Cols, KH, KM, KL>(tt, a, blocks, threads, lds, s);
+#if HNTT_WORD == 32
+  if constexpr (!Cols) {
+    if (whole && (n == 9 || n == 10)) {  // one-pass transforms: a full wave each
+      switch (n) {
+        HNTT_CASE(9, 3, 3, 3)
+        HNTT_CASE(10, 4, 3, 3)
+        default: break;
+      }
+    }
+  }
+#else
+  (void)whole;
+#endif
   switch (n) {
     HNTT_CASE(1, 0, 0, 1)
     HNTT_CASE(2, 0, 0, 2)
@@ -639,9 +653,10 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   if (units < 1 || pp.nbatch < 1) return hipErrorInvalidValue;
   if (!pp.table && pp.nbatch > kMaxBatchPerLaunch) return hipErrorInvalidValue;
   if (pp.table && (pp.nslots < 1 || pp.nslots > kMaxSlots)) return hipErrorInvalidValue;
-  const int threads = pass_tpt(n, HNTT_WORD) * pp.group;
+  const bool whole = pp.kind == PassKind::kWhole;
+  const int threads = pass_tpt(n, HNTT_WORD, whole) * pp.group;
   const size_t lds = pass_lds_bytes(pp);
-  if (threads > kMaxPassThreads || (lds == 0 && pass_split(n, HNTT_WORD).kh > 0)) return hipErrorInvalidValue;
+  if (threads > kMaxPassThreads || (lds == 0 && pass_split(n, HNTT_WORD, whole).kh > 0)) return hipErrorInvalidValue;
   const long long total = (long long)units * pp.nbatch;
   if (total > (1ll << 30)) return hipErrorInvalidValue;
   HNTT_NS::KernelArgs a{};
@@ -667,14 +682,14 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   const bool tt = pp.table ? pp.slots[0].tt != nullptr : pp.tt != nullptr;
   switch (pp.policy) {
     case kPolicyLazy:
-      return cols ? dispatch_n<kPolicyLazy, true>(n, tt, a, blocks, threads, lds, stream)
-                  : dispatch_n<kPolicyLazy, false>(n, tt, a, blocks, threads, lds, stream);
+      return cols ? dispatch_n<kPolicyLazy, true>(n, whole, tt, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyLazy, false>(n, whole, tt, a, blocks, threads, lds, stream);
     case kPolicyPlain:
-      return cols ? dispatch_n<kPolicyPlain, true>(n, tt, a, blocks, threads, lds, stream)
-                  : dispatch_n<kPolicyPlain, false>(n, tt, a, blocks, threads, lds, stream);
+      return cols ? dispatch_n<kPolicyPlain, true>(n, whole, tt, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyPlain, false>(n, whole, tt, a, blocks, threads, lds, stream);
     case kPolicyMont:
-      return cols ? dispatch_n<kPolicyMont, true>(n, tt, a, blocks, threads, lds, stream)
-                  : dispatch_n<kPolicyMont, false>(n, tt, a, blocks, threads, lds, stream);
+      return cols ? dispatch_n<kPolicyMont, true>(n, whole, tt, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyMont, false>(n, whole, tt, a, blocks, threads, lds, stream);
     default:
       return hipErrorInvalidValue;
   }
