@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-mont", action="store_true", help="skip the Montgomery-butterfly (Algorithm 5) comparison")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in schedule instead of the autotuner's")
     ap.add_argument("--workload", default="batch64",
-                    choices=["batch64", "single1k", "u64", "polymul", "serving", "bigmul", "table1"],
+                    choices=["batch64", "single1k", "u64", "polymul", "serving", "bigmul", "table1", "pointwise"],
                     help="batch64 (default, the headline line); the others print their own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for HBM byte counters)")

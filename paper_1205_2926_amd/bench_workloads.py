@@ -3,6 +3,7 @@
 single1k  one forward NTT of 1024 residues (latency, lazy and plain)
 u64       8 NTTs of length 2^22 over the 62-bit prime, forward + inverse, lazy vs plain vs Montgomery
 bigmul    16 products of 2^20-limb (32 Mbit) integers, three primes + device carry scan
+pointwise c = a b mod p over 64 x 2^20 u32 words (HBM roofline of the standalone product)
 table1    host CPU: Algorithm 2 vs Algorithm 3, one transform of 2^11 over the 62-bit prime
           (the design of the paper's Table 1), time per butterfly on one core
 polymul   4096 products with log-uniform lengths 2^8..2^16, three primes + CRT, one graph launch
@@ -229,3 +230,25 @@ def table1(args):
             "value": r["alg3"]["ns_per_butterfly"], **r,
             "paper_table1_cycles": {"Westmere": {"alg2": 10.1, "alg3": 6.9}, "Sandy Bridge": {"alg2": 9.1, "alg3": 5.9},
                                     "Piledriver": {"alg2": 13.9, "alg3": 12.0}}}
+
+
+def pointwise(args):
+    """hntt_pointwise_mul over 64 x 2^20 u32 residues (two reads and one write of 4 bytes per
+    word): achieved bandwidth against the 8 TB/s HBM peak; checked against the oracle on a row."""
+    import oracle
+    from .workloads import P30, uniform_residues
+    n = 64 << 20
+    a_np = uniform_residues(9, n, P30, np.uint32)
+    b_np = uniform_residues(10, n, P30, np.uint32)
+    ctx = hntt.Context(0)
+    a = torch.from_numpy(a_np.view(np.int32)).cuda()
+    b = torch.from_numpy(b_np.view(np.int32)).cuda()
+    c = torch.empty_like(a)
+    ms = _events_ms(lambda: ctx.pointwise_mul(a, b, c, P30), max(10, args.steps))
+    got = c[: 1 << 16].cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal(got, oracle.Oracle().pointwise(a_np[: 1 << 16], b_np[: 1 << 16], P30)), "pointwise mismatch"
+    ctx.close()
+    gbs = 12 * n / (ms / 1e3) / 1e9
+    return {"metric": "pointwise product bandwidth, 64 x 2^20 u32 words", "unit": "GB/s", "value": gbs,
+            "ms_per_call": ms, "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                                            "frac": gbs / 8000.0}}

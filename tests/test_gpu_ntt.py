@@ -297,6 +297,9 @@ def test_pointwise_mul(ctx, orc, wb, p):
     tc = torch.empty_like(ta)
     ctx.pointwise_mul(ta, tb, tc, p)
     np.testing.assert_array_equal(host(tc, dt).astype(np.uint64), orc.pointwise(a, b, p))
+    tc2 = torch.zeros_like(ta)
+    ctx.pointwise_mul(ta[1:], tb[1:], tc2[1:], p)  # operands not 16-byte aligned: word-by-word path
+    np.testing.assert_array_equal(host(tc2, dt)[1:].astype(np.uint64), orc.pointwise(a[1:], b[1:], p))
     ctx.pointwise_mul(ta, tb, ta, p)  # in place
     np.testing.assert_array_equal(host(ta, dt).astype(np.uint64), orc.pointwise(a, b, p))
 
