@@ -108,6 +108,9 @@ struct PassParams {
   // (this transform's own words are left stale).  Used by the polynomial product:
   // B_k's last pass multiplies into A_k.
   uint32_t pm_off;
+  // First forward pass only: the upper half of every input (positions >= 2^l / 2)
+  // is known to be zero, so it is not read (the padded operands of a product).
+  bool zero_upper;
   // Batched form: transforms listed in a device table, each with its prime's slot;
   // when `table` is set, p/tw/tt/scale above are ignored and slots[] is used.
   const XformEntry *table;

@@ -186,10 +186,12 @@ constexpr int kVec = 16 / sizeof(T);
 // Src/Dst provide load2/store2 of one position given as a per-lane part plus a
 // uniform part with disjoint bits, and load_vec/store_vec of kVec consecutive
 // positions when their kContig flag is set.
+// zero_upper (first round of a forward transform only, where the round's top
+// bit is the position's top bit): words of the upper half read as 0 unloaded.
 template <int Pol, int N_LOG, int K, bool LowRound, class Src, class Dst>
 __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol> *tws,
                                        const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m, const Src &src,
-                                       const Dst &dst) {
+                                       const Dst &dst, bool zero_upper = false) {
   constexpr int groups = 1 << (N_LOG - K);
   constexpr int M = 1 << K;
 #pragma unroll 1
@@ -199,10 +201,22 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
     T v[M];
     if constexpr (LowRound && Src::kContig && M >= kVec) {
 #pragma unroll
-      for (int e = 0; e < M; e += kVec) src.load_vec(base + e, &v[e]);
+      for (int e = 0; e < M; e += kVec) {
+        if (zero_upper && ((e >> (K - 1)) & 1)) {  // the whole vector lies in the upper half
+#pragma unroll
+          for (int i = 0; i < kVec; ++i) v[e + i] = 0;
+        } else {
+          src.load_vec(base + e, &v[e]);
+          if (zero_upper) {
+#pragma unroll
+            for (int i = 0; i < kVec; ++i)
+              if (((e + i) >> (K - 1)) & 1) v[e + i] = 0;
+          }
+        }
+      }
     } else {
 #pragma unroll
-      for (int e = 0; e < M; ++e) v[e] = src.load2(base, e << b_lo);
+      for (int e = 0; e < M; ++e) v[e] = (zero_upper && ((e >> (K - 1)) & 1)) ? (T)0 : src.load2(base, e << b_lo);
     }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
@@ -255,6 +269,7 @@ struct KernelArgs {
   int normalize;              // reduce the final output to [0,p)
   int scale;                  // whole inverse: multiply by L^-1 (slot scale_w, scale_wp)
   uint32_t pm_off;            // fused pointwise product into the partner transform (0: off)
+  int zero_upper;             // first forward pass: the upper half of every input is zero, not read
   SlotParams slots[kMaxSlots];
 };
 
@@ -503,13 +518,13 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
 
     if constexpr (KH == 0) {
       // one round, HBM to HBM
-      round_k<Pol, N_LOG, KL, true>(0, t, TPT, nullptr, twg, m, gio, gio);
+      round_k<Pol, N_LOG, KL, true>(0, t, TPT, nullptr, twg, m, gio, gio, !kInverse && a.zero_upper);
     } else {
       for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = twg[i];
       const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
       if constexpr (!kInverse) {
         __syncthreads();  // twiddle table staged
-        round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio);
+        round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio, a.zero_upper != 0);
         __syncthreads();
         if constexpr (KM > 0) {
           round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
@@ -672,6 +687,8 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   // the fused product belongs to the final forward pass (rows or whole) only
   if (pp.pm_off && (pp.inverse || pp.kind == PassKind::kCols || !pp.normalize)) return hipErrorInvalidValue;
   a.pm_off = pp.pm_off;
+  if (pp.zero_upper && (pp.inverse || pp.kind == PassKind::kRows)) return hipErrorInvalidValue;
+  a.zero_upper = pp.zero_upper ? 1 : 0;
   if (pp.table) {
     for (int i = 0; i < pp.nslots; ++i) a.slots[i] = pp.slots[i];
   } else {

@@ -87,7 +87,7 @@ int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_
       return perr(ctx, HNTT_EUNSUPPORTED, "product %zu: padded length 2^%d above 2^%d", i, l, kMaxPolyLog);
     sz->logs[i] = l;
     sz->ws_words += 6ull << l;
-    sz->chunks_ws += ((1ull << l) + kChunkWords - 1) / kChunkWords;
+    sz->chunks_ws += ((1ull << l) / 2 + kChunkWords - 1) / kChunkWords;  // preparation covers the lower half
     sz->chunks_out += ((uint64_t)d.na + d.nb - (big ? 0 : 1) + kChunkWords - 1) / kChunkWords;
     sz->class_count[l]++;
   }
@@ -182,6 +182,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
     pp.group = 1;
     pp.normalize = true;
     pp.pm_off = pm_off;
+    pp.zero_upper = !inverse;  // padded operands: the upper half is zero
     slots_for(pp, 0);
     if ((e = launch_pass(pp, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly whole)");
     return HNTT_OK;
@@ -200,6 +201,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
   cols.normalize = inverse;
   rows.normalize = !inverse;
   rows.pm_off = pm_off;
+  cols.zero_upper = !inverse;  // padded operands: rows in the upper half are zero
   if (!inverse) {
     if ((e = launch_pass(cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
     if ((e = launch_pass(rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
@@ -317,7 +319,7 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
     const hntt_poly_desc &d = descs[i];
     const int l = logs[i];
     hp[i] = PolyPair{d.a, d.b, d.out, d.na, d.nb, (uint32_t)l, (uint32_t)co_i, woff};
-    for (uint64_t s = 0; s < (1ull << l); s += kChunkWords) hcw[cw_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
+    for (uint64_t s = 0; s < (1ull << l) / 2; s += kChunkWords) hcw[cw_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
     const uint64_t nout = (uint64_t)d.na + d.nb - (big ? 0 : 1);
     for (uint64_t s = 0; s < nout; s += kChunkWords) hco[co_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
     woff += 6ull << l;

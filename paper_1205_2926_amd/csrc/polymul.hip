@@ -35,7 +35,9 @@ __global__ void __launch_bounds__(kThreads) k_poly_prep(PolyArgs args) {
     const PolyPair pp = args.pairs[ce.pair];
     const uint32_t L = 1u << pp.log2_len;
     uint32_t *ws = args.workspace + pp.ws_off;
-    for (uint32_t j = ce.start + threadIdx.x; j < ce.start + kChunk && j < L; j += kThreads) {
+    // the lower half only: na, nb <= L / 2, and the first forward pass reads the
+    // upper half as zero without loading it
+    for (uint32_t j = ce.start + threadIdx.x; j < ce.start + kChunk && j < L / 2; j += kThreads) {
       const uint32_t av = j < pp.na ? pp.a[j] : 0u;
       const uint32_t bv = j < pp.nb ? pp.b[j] : 0u;
 #pragma unroll

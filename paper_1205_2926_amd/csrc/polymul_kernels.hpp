@@ -39,7 +39,7 @@ struct CrtConst {
 
 struct PolyArgs {
   const PolyPair *pairs;
-  const ChunkEntry *chunks_ws;   // chunks over the padded length L of every product
+  const ChunkEntry *chunks_ws;   // chunks over the lower half (L / 2 words) of every product
   int nchunks_ws;
   const ChunkEntry *chunks_out;  // chunks over the na + nb - 1 output coefficients
                                  // (large-integer mode: over the na + nb limbs)
