@@ -186,12 +186,13 @@ constexpr int kVec = 16 / sizeof(T);
 // Src/Dst provide load2/store2 of one position given as a per-lane part plus a
 // uniform part with disjoint bits, and load_vec/store_vec of kVec consecutive
 // positions when their kContig flag is set.
-// zero_upper (first round of a forward transform only, where the round's top
-// bit is the position's top bit): words of the upper half read as 0 unloaded.
-template <int Pol, int N_LOG, int K, bool LowRound, class Src, class Dst>
+// ZU (first round of a forward transform only, where the round's top bit is the
+// position's top bit): words of the upper half read as 0 without being loaded.
+// A template parameter, so that rounds without it compile exactly as before.
+template <int Pol, int N_LOG, int K, bool LowRound, bool ZU = false, class Src, class Dst>
 __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol> *tws,
                                        const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m, const Src &src,
-                                       const Dst &dst, bool zero_upper = false) {
+                                       const Dst &dst) {
   constexpr int groups = 1 << (N_LOG - K);
   constexpr int M = 1 << K;
 #pragma unroll 1
@@ -202,12 +203,12 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
     if constexpr (LowRound && Src::kContig && M >= kVec) {
 #pragma unroll
       for (int e = 0; e < M; e += kVec) {
-        if (zero_upper && ((e >> (K - 1)) & 1)) {  // the whole vector lies in the upper half
+        if (ZU && ((e >> (K - 1)) & 1)) {  // the whole vector lies in the upper half
 #pragma unroll
           for (int i = 0; i < kVec; ++i) v[e + i] = 0;
         } else {
           src.load_vec(base + e, &v[e]);
-          if (zero_upper) {
+          if constexpr (ZU) {
 #pragma unroll
             for (int i = 0; i < kVec; ++i)
               if (((e + i) >> (K - 1)) & 1) v[e + i] = 0;
@@ -216,7 +217,7 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < M; ++e) v[e] = (zero_upper && ((e >> (K - 1)) & 1)) ? (T)0 : src.load2(base, e << b_lo);
+      for (int e = 0; e < M; ++e) v[e] = (ZU && ((e >> (K - 1)) & 1)) ? (T)0 : src.load2(base, e << b_lo);
     }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
@@ -423,6 +424,21 @@ struct LdsIO {
   }
 };
 
+// An LDS tile read as the input of a pass: words go through the pass's input
+// edge (the split twiddle) as they leave LDS.
+template <class EdgeT>
+struct LdsEdgeIO {
+  static constexpr bool kContig = true;
+  LdsIO<false> lio;
+  EdgeT edge;
+  __device__ __forceinline__ T load2(int lp, int up) const { return edge.in(lio.load2(lp, up), lp, up); }
+  __device__ __forceinline__ void load_vec(int pos, T *v) const {
+    lio.load_vec(pos, v);
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) v[i] = edge.in(v[i], pos + i);
+  }
+};
+
 // Padded LDS words per sub-transform (rows: row pitch; cols: rows of the tile).
 template <bool Cols>
 constexpr int padded_len(int N) {
@@ -518,13 +534,35 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
 
     if constexpr (KH == 0) {
       // one round, HBM to HBM
-      round_k<Pol, N_LOG, KL, true>(0, t, TPT, nullptr, twg, m, gio, gio, !kInverse && a.zero_upper);
+      if (!kInverse && a.zero_upper) round_k<Pol, N_LOG, KL, true, true>(0, t, TPT, nullptr, twg, m, gio, gio);
+      else round_k<Pol, N_LOG, KL, true>(0, t, TPT, nullptr, twg, m, gio, gio);
     } else {
       for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = twg[i];
       const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
       if constexpr (!kInverse) {
-        __syncthreads();  // twiddle table staged
-        round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio, a.zero_upper != 0);
+        // Rows with fewer than 32 threads per row: a high-round load instruction would
+        // cover under 128 bytes of each row, so the tile is first copied into LDS with
+        // consecutive lanes on consecutive 16 bytes, and the high round reads it there.
+        constexpr bool kCopyIn = !Cols && TPT < 32;
+        if constexpr (kCopyIn) {
+          constexpr int kPitch = padded_len<false>(N);
+          constexpr int kChunks = N / kVec;
+          const HNTT_GLOBAL T *const rows0 = gbase + (size_t)unit * G * N;
+          for (int i = threadIdx.x; i < G * kChunks; i += blockDim.x) {
+            const int row = i / kChunks, c = (i % kChunks) * kVec;
+            Vec16 q = {0, 0, 0, 0};
+            if (!(a.zero_upper && c >= N / 2))
+              q = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(rows0 + (size_t)row * N + c);
+            *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2)) = q;
+          }
+          __syncthreads();  // tile and twiddle table staged
+          const LdsEdgeIO<EdgeT> lin{lio, edge};
+          round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, lin, lio);
+        } else {
+          __syncthreads();  // twiddle table staged
+          if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio);
+          else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio);
+        }
         __syncthreads();
         if constexpr (KM > 0) {
           round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
