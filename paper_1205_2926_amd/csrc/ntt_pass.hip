@@ -186,13 +186,19 @@ constexpr int kVec = 16 / sizeof(T);
 // Src/Dst provide load2/store2 of one position given as a per-lane part plus a
 // uniform part with disjoint bits, and load_vec/store_vec of kVec consecutive
 // positions when their kContig flag is set.
+// after_load runs once per thread, after the loads of its first group are issued
+// and before the stages (the twiddle staging below uses it to overlap the two).
 // ZU (first round of a forward transform only, where the round's top bit is the
 // position's top bit): words of the upper half read as 0 without being loaded.
 // A template parameter, so that rounds without it compile exactly as before.
-template <int Pol, int N_LOG, int K, bool LowRound, bool ZU = false, class Src, class Dst>
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+template <int Pol, int N_LOG, int K, bool LowRound, bool ZU = false, class Src, class Dst, class Hook = NoHook>
 __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol> *tws,
                                        const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m, const Src &src,
-                                       const Dst &dst) {
+                                       const Dst &dst, const Hook &after_load = Hook{}) {
   constexpr int groups = 1 << (N_LOG - K);
   constexpr int M = 1 << K;
 #pragma unroll 1
@@ -219,6 +225,9 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
 #pragma unroll
       for (int e = 0; e < M; ++e) v[e] = (ZU && ((e >> (K - 1)) & 1)) ? (T)0 : src.load2(base, e << b_lo);
     }
+    // Every thread runs groups / tpt >= 1 iterations, so a hook that synchronises
+    // the workgroup is reached once by all threads.
+    if (gi == t) after_load();
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       const int hb = kInverse ? s : K - 1 - s;
@@ -439,6 +448,31 @@ struct LdsEdgeIO {
   }
 };
 
+// Copy of the N-entry heap twiddle table into LDS, in two steps so that its global
+// loads are in flight together with the tile's: load() issues up to kR loads per
+// thread into registers, store() writes them to LDS (and copies any remainder).
+template <int Pol, int N>
+struct TwStage {
+  static constexpr int kR = 4;
+  TwT<Pol> r[kR];
+  int nthr;  // threads in the workgroup
+  __device__ __forceinline__ void load(const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) {
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const int i = threadIdx.x + j * nthr;
+      if (i < N) r[j] = twg[i];
+    }
+  }
+  __device__ __forceinline__ void store(TwT<Pol> *tws, const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) const {
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      const int i = threadIdx.x + j * nthr;
+      if (i < N) tws[i] = r[j];
+    }
+    for (int i = threadIdx.x + kR * nthr; i < N; i += nthr) tws[i] = twg[i];
+  }
+};
+
 // Padded LDS words per sub-transform (rows: row pitch; cols: rows of the tile).
 template <bool Cols>
 constexpr int padded_len(int N) {
@@ -537,7 +571,12 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
       if (!kInverse && a.zero_upper) round_k<Pol, N_LOG, KL, true, true>(0, t, TPT, nullptr, twg, m, gio, gio);
       else round_k<Pol, N_LOG, KL, true>(0, t, TPT, nullptr, twg, m, gio, gio);
     } else {
-      for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = twg[i];
+      // The twiddle table's loads are issued first and written to LDS only after
+      // the tile's loads are in flight: one memory round trip before the stages.
+      const int nthr = G * TPT;  // blockDim.x
+      TwStage<Pol, N> stage;
+      stage.nthr = nthr;
+      stage.load(twg);
       const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
       if constexpr (!kInverse) {
         // Rows with fewer than 32 threads per row: a high-round load instruction would
@@ -547,21 +586,49 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
         if constexpr (kCopyIn) {
           constexpr int kPitch = padded_len<false>(N);
           constexpr int kChunks = N / kVec;
+          constexpr int kPer = kChunks / TPT;  // vectors per thread
+          static_assert(kPer * TPT == kChunks && kPer % 2 == 0, "copy-in covers the tile exactly");
           const HNTT_GLOBAL T *const rows0 = gbase + (size_t)unit * G * N;
-          for (int i = threadIdx.x; i < G * kChunks; i += blockDim.x) {
-            const int row = i / kChunks, c = (i % kChunks) * kVec;
-            Vec16 q = {0, 0, 0, 0};
-            if (!(a.zero_upper && c >= N / 2))
-              q = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(rows0 + (size_t)row * N + c);
-            *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2)) = q;
-          }
-          __syncthreads();  // tile and twiddle table staged
-          const LdsEdgeIO<EdgeT> lin{lio, edge};
-          round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, lin, lio);
-        } else {
+          // ZU: only the lower half of each row is copied, and the high round reads
+          // the upper half as zero (a compile-time choice: no per-lane branch between
+          // a load and its use).
+          const auto copy_in = [&](auto zu_tag) {
+            constexpr bool ZU = decltype(zu_tag)::value;
+            constexpr int kCh = ZU ? kChunks / 2 : kChunks;  // chunks read per row
+            constexpr int kLoad = ZU ? kPer / 2 : kPer;
+            Vec16 q[kLoad];
+#pragma unroll
+            for (int j = 0; j < kLoad; ++j) {
+              const int i = threadIdx.x + j * nthr;
+              q[j] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(rows0 + (size_t)(i / kCh) * N + (i % kCh) * kVec);
+            }
+#pragma unroll
+            for (int j = 0; j < kLoad; ++j) {
+              const int i = threadIdx.x + j * nthr;
+              const int row = i / kCh, c = (i % kCh) * kVec;
+              *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2)) = q[j];
+            }
+            stage.store(tws, twg);
+            __syncthreads();  // tile and twiddle table staged
+            const LdsEdgeIO<EdgeT> lin{lio, edge};
+            round_k<Pol, N_LOG, KH, false, ZU>(KM + KL, t, TPT, tws, twg, m, lin, lio);
+          };
+          if (a.zero_upper) copy_in(std::true_type{});
+          else copy_in(std::false_type{});
+        } else if constexpr (TT) {
+          // the split twiddle's products follow the loads and would all have to
+          // finish before a barrier placed after them: the table goes first
+          stage.store(tws, twg);
           __syncthreads();  // twiddle table staged
           if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio);
           else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio);
+        } else {
+          const auto staged = [&]() {
+            stage.store(tws, twg);
+            __syncthreads();  // twiddle table staged
+          };
+          if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio, staged);
+          else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio, staged);
         }
         __syncthreads();
         if constexpr (KM > 0) {
@@ -576,32 +643,53 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           // and write the tile out with consecutive lanes on consecutive 16 bytes.
           round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
+          // (every thread moves kPer vectors; the partner words of the fused product
+          // are all requested before the first is used)
           constexpr int kPitch = padded_len<false>(N);
           constexpr int kChunks = N / kVec;
-          HNTT_GLOBAL T *const rows0 = gbase + (size_t)unit * G * N;
-          for (int i = threadIdx.x; i < G * kChunks; i += blockDim.x) {
+          constexpr int kPer = kChunks / TPT;
+          static_assert(kPer * TPT == kChunks, "copy-out covers the tile exactly");
+          const size_t tile0 = (size_t)unit * G * N;
+          Vec16 o[kPer];
+#pragma unroll
+          for (int j = 0; j < kPer; ++j) {
+            const int i = threadIdx.x + j * nthr;
             const int row = i / kChunks, c = (i % kChunks) * kVec;
             const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2));
-            Vec16 o;
             const T *w = reinterpret_cast<const T *>(&q);
-            T *wo = reinterpret_cast<T *>(&o);
+            T *wo = reinterpret_cast<T *>(&o[j]);
 #pragma unroll
-            for (int j = 0; j < kVec; ++j) wo[j] = edge.out(w[j], c + j);
-            if (gio.pm) {  // fused pointwise product into the partner transform
-              HNTT_GLOBAL Vec16 *dst =
-                  reinterpret_cast<HNTT_GLOBAL Vec16 *>(gio.pm + (size_t)unit * G * N + (size_t)row * N + c);
-              const Vec16 pa = *dst;
-              const T *pw = reinterpret_cast<const T *>(&pa);
+            for (int e = 0; e < kVec; ++e) wo[e] = edge.out(w[e], c + e);
+          }
+          HNTT_GLOBAL T *const out0 = (gio.pm ? gio.pm : gbase) + tile0;
+          if (gio.pm) {  // fused pointwise product into the partner transform
+            Vec16 pa[kPer];
 #pragma unroll
-              for (int j = 0; j < kVec; ++j) wo[j] = pmul_word(wo[j], pw[j], m, gio.r2);
-              *dst = o;
-            } else {
-              *reinterpret_cast<HNTT_GLOBAL Vec16 *>(rows0 + (size_t)row * N + c) = o;
+            for (int j = 0; j < kPer; ++j) {
+              const int i = threadIdx.x + j * nthr;
+              pa[j] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(out0 + (size_t)(i / kChunks) * N +
+                                                                    (i % kChunks) * kVec);
             }
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+              const T *pw = reinterpret_cast<const T *>(&pa[j]);
+              T *wo = reinterpret_cast<T *>(&o[j]);
+#pragma unroll
+              for (int e = 0; e < kVec; ++e) wo[e] = pmul_word(wo[e], pw[e], m, gio.r2);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < kPer; ++j) {
+            const int i = threadIdx.x + j * nthr;
+            *reinterpret_cast<HNTT_GLOBAL Vec16 *>(out0 + (size_t)(i / kChunks) * N + (i % kChunks) * kVec) = o[j];
           }
         }
       } else {
+        // With the split twiddle the table is written first: keeping its registers
+        // live through the round costs the round's loads their overlap.
+        if constexpr (TT) stage.store(tws, twg);
         round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, gio, lio);
+        if constexpr (!TT) stage.store(tws, twg);
         __syncthreads();  // tile and twiddle table complete
         if constexpr (KM > 0) {
           round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
