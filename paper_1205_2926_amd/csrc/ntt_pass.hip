@@ -453,7 +453,7 @@ struct LdsEdgeIO {
 // thread into registers, store() writes them to LDS (and copies any remainder).
 template <int Pol, int N>
 struct TwStage {
-  static constexpr int kR = 4;
+  static constexpr int kR = 8;
   TwT<Pol> r[kR];
   int nthr;  // threads in the workgroup
   __device__ __forceinline__ void load(const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) {
