@@ -300,7 +300,15 @@ __device__ __forceinline__ T pmul_word(T a, T b, const Mod &m, T r2) {
 // small enough to stay in the L1/L2 caches.  SIGMA is the bit boundary of the
 // pass's first register round, so one factor is fixed per thread group and the
 // other is shared by all lanes of a sub-transform.  TT = false: no split twiddle.
-template <int Pol, bool Cols, bool TT, int N_LOG, int SIGMA>
+// Out fixes what out() does: kOutRaw passes words through (the first pass of a
+// two-pass transform), kOutNorm reduces them to [0,p), kOutCond reduces them
+// with p replaced by 0 when normalisation is off (the same instructions either
+// way, no select), kOutAny follows the runtime flags (whole inverse transforms,
+// which may also scale by L^-1).  The final round of a pass picks its variant
+// with one uniform branch: with the flags tested per word, the compiler computes
+// the reduction for every word and selects afterwards, also when it is not wanted.
+constexpr int kOutRaw = 0, kOutNorm = 1, kOutAny = 2, kOutCond = 3;
+template <int Pol, bool Cols, bool TT, int N_LOG, int SIGMA, int Out = kOutAny>
 struct Edge {
   Mod m;
   int normalize, scale;
@@ -323,8 +331,18 @@ struct Edge {
     return x;
   }
   __device__ __forceinline__ T in(T x, int pos) const { return in(x, pos, 0); }
+  template <int O>
+  __device__ __forceinline__ Edge<Pol, Cols, TT, N_LOG, SIGMA, O> with_out() const {
+    return {m, normalize, scale, sw, swp, tt, tt_off, tt_step};
+  }
   __device__ __forceinline__ T out(T x, int pos) const {
-    if constexpr (!Cols && kInverse) {
+    if constexpr (Out == kOutRaw) {
+      return x;
+    } else if constexpr (Out == kOutNorm) {
+      return reduce_final<Pol>(x, m.p);
+    } else if constexpr (Out == kOutCond) {
+      return reduce_final<Pol>(x, normalize ? m.p : (T)0);
+    } else if constexpr (!Cols && kInverse) {
       if (scale) {  // whole inverse transform: times L^-1, then reduced
         if constexpr (Pol == kPolicyMont) x = mont_lazy<Wd>(x, sw, m.p, m.j);
         else x = shoup_lazy<Wd>(x, sw, swp, m.p);
@@ -353,6 +371,19 @@ struct GlobalIO {
   uint32_t off;
   uint32_t stride;
   EdgeT edge;
+  // the same view with another output variant of the edge
+  template <int O>
+  __device__ __forceinline__ auto with_out() const {
+    GlobalIO<Cols, decltype(edge.template with_out<O>())> g;
+    g.base = base;
+    g.pm = pm;
+    g.r2 = r2;
+    g.rsrc = rsrc;
+    g.off = off;
+    g.stride = stride;
+    g.edge = edge.template with_out<O>();
+    return g;
+  }
   __device__ __forceinline__ T load2(int lp, int up) const {
     if constexpr (Cols) {
       const T x = buf_load(rsrc, (off + (uint32_t)lp * stride) * (uint32_t)sizeof(T),
@@ -636,7 +667,9 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           __syncthreads();
         }
         if constexpr (Cols) {
-          round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, gio);
+          // the forward column pass is always the first of two: its output is never
+          // reduced (the launcher rejects the flag)
+          round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, gio.template with_out<kOutRaw>());
         } else {
           // Rows: a thread's low-round outputs are 2^KL consecutive words, so direct
           // stores would put neighbouring lanes 2^KL words apart.  Stage them in LDS
@@ -650,6 +683,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           constexpr int kPer = kChunks / TPT;
           static_assert(kPer * TPT == kChunks, "copy-out covers the tile exactly");
           const size_t tile0 = (size_t)unit * G * N;
+          const auto ed = edge.template with_out<kOutCond>();
           Vec16 o[kPer];
 #pragma unroll
           for (int j = 0; j < kPer; ++j) {
@@ -659,7 +693,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
             const T *w = reinterpret_cast<const T *>(&q);
             T *wo = reinterpret_cast<T *>(&o[j]);
 #pragma unroll
-            for (int e = 0; e < kVec; ++e) wo[e] = edge.out(w[e], c + e);
+            for (int e = 0; e < kVec; ++e) wo[e] = ed.out(w[e], c + e);
           }
           HNTT_GLOBAL T *const out0 = (gio.pm ? gio.pm : gbase) + tile0;
           if (gio.pm) {  // fused pointwise product into the partner transform
@@ -695,7 +729,16 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
         }
-        round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, lio, gio);
+        const auto last = [&](const auto &dst) {
+          round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, lio, dst);
+        };
+        if constexpr (Cols) {
+          last(gio.template with_out<kOutCond>());  // column passes never scale
+        } else {
+          if (a.scale) last(gio);  // whole inverse: times L^-1
+          else if (a.normalize) last(gio.template with_out<kOutNorm>());
+          else last(gio.template with_out<kOutRaw>());
+        }
       }
     }
   }
@@ -812,6 +855,7 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   a.scale = (pp.kind == PassKind::kWhole && pp.inverse) ? 1 : 0;
   // the fused product belongs to the final forward pass (rows or whole) only
   if (pp.pm_off && (pp.inverse || pp.kind == PassKind::kCols || !pp.normalize)) return hipErrorInvalidValue;
+  if (pp.kind == PassKind::kCols && !pp.inverse && pp.normalize) return hipErrorInvalidValue;
   a.pm_off = pp.pm_off;
   if (pp.zero_upper && (pp.inverse || pp.kind == PassKind::kRows)) return hipErrorInvalidValue;
   a.zero_upper = pp.zero_upper ? 1 : 0;
