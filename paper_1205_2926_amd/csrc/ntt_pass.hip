@@ -395,7 +395,7 @@ struct GlobalIO {
   }
   __device__ __forceinline__ void store2(int lp, int up, T x) const {
     x = edge.out(x, lp + up);
-    if constexpr (!Cols) {
+    if constexpr (!Cols && !kInverse) {  // (the fused product ends forward transforms only)
       if (pm) {
         HNTT_GLOBAL T *q = pm + off + (uint32_t)(lp + up);
         *q = pmul_word(x, *q, edge.m, r2);
@@ -421,7 +421,7 @@ struct GlobalIO {
     T *w = reinterpret_cast<T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) w[i] = edge.out(v[i], pos + i);
-    if (pm) {
+    if (!kInverse && pm) {
       HNTT_GLOBAL Vec16 *dst = reinterpret_cast<HNTT_GLOBAL Vec16 *>(pm + (off + (uint32_t)pos));
       const Vec16 pa = *dst;
       const T *pw = reinterpret_cast<const T *>(&pa);
