@@ -11,7 +11,11 @@ namespace hntt {
 
 using u128 = unsigned __int128;
 
-inline uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+// a b mod m (a 64-bit division when all three are below 2^32)
+inline uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) {
+  if ((a | b | m) >> 32 == 0) return a * b % m;
+  return (uint64_t)((u128)a * b % m);
+}
 
 inline uint64_t powmod(uint64_t a, uint64_t e, uint64_t m) {
   uint64_t r = 1 % m;
@@ -83,6 +87,7 @@ inline uint64_t primitive_root(uint64_t p) {
 
 // floor(w * 2^bits / p) for w < p < 2^bits, bits in {32, 64}.
 inline uint64_t shoup_constant(uint64_t w, uint64_t p, int bits) {
+  if (bits == 32) return (w << 32) / p;
   return (uint64_t)(((u128)w << bits) / p);
 }
 
