@@ -139,14 +139,14 @@ def serving(args):
 
     def at_rate(rate, seed=5):
         count = int(min(800, max(60, rate * 0.5)))
-        reqs = make_requests(seed=seed, count=count, rate_per_s=rate)
+        reqs = make_requests(seed=seed, count=count, rate_per_s=rate, client_out=True)
         st = serve(reqs)
         st.update({"offered_rate": rate})
         return st, reqs
 
     # warm the twiddle tables of every length class
     serve(make_requests(seed=50, count=40, rate_per_s=1e9))
-    burst = serve(make_requests(seed=5, count=400, rate_per_s=1e9))  # everything queued at time 0
+    burst = serve(make_requests(seed=5, count=400, rate_per_s=1e9, client_out=True))  # all queued at time 0
     # saturation: raise the offered rate until the server falls behind (achieved < 90% offered)
     rate, probes = burst["products_per_s"], []
     for _ in range(10):
@@ -169,7 +169,8 @@ def serving(args):
         assert int(r.result[k]) == orc.product_coeff(r.a, r.b, k)
     ctx.close()
     return {"metric": "serving: products/s at saturation, p50/p99 latency vs offered rate", "unit": "products/s",
-            "value": mu, "workload": "Poisson stream, n log-uniform 2^10..2^20, 3 primes + CRT, budget 8 GiB",
+            "value": mu, "workload": "Poisson stream, n log-uniform 2^10..2^20, 3 primes + CRT, budget 8 GiB, "
+                                     "results written into client-provided buffers",
             "burst": {k: burst[k] for k in ("requests", "products_per_s", "p50_ms", "p99_ms", "batches")},
             "saturation_probes": probes,
             "sweep": [{k: st[k] for k in ("offered_fraction", "offered_rate", "products_per_s", "p50_ms", "p99_ms",

@@ -17,8 +17,10 @@
 // With KH = 0 there is one round and no LDS tile.  Global loads and stores are
 // issued directly by the rounds that touch HBM; lanes are laid out so that each
 // memory instruction covers contiguous words (columns fastest in a cols pass,
-// positions fastest in a rows pass), and the forward row pass writes its output
-// through LDS so that consecutive lanes store consecutive 16 bytes.
+// positions fastest in a rows pass).  The forward row pass writes its output
+// through LDS so that consecutive lanes store consecutive 16 bytes, and when a
+// row has fewer than 32 threads it also reads its input through LDS.  Every
+// thread issues all of its loads for such an LDS copy before the first wait.
 //
 // Twiddles of the high and middle rounds depend on the thread's low position
 // bits and are read from an LDS copy of the table; twiddles of the low round
@@ -28,6 +30,8 @@
 // twiddle of a two-pass transform is applied where the data enters the second
 // pass (Edge), and the final forward pass of a polynomial product can multiply
 // its output into a partner transform (the pointwise product, GlobalIO::pm).
+#include <type_traits>
+
 #include "modarith.hpp"
 #include "ntt_kernels.hpp"
 

@@ -10,8 +10,9 @@ loop on the host:
 * launches each admitted group as one batch (``hntt_polymul_plan_*``: three
   primes + CRT) on the next idle HIP stream, so batches that are admitted
   while others are still on the GPU run concurrently with them;
-* retires batches as their completion events fire, copies results back, frees
-  their memory, and admits whatever now fits.
+* retires batches as their completion events fire, copies results back (into
+  buffers the client provides, when it does), frees their memory, and admits
+  whatever now fits.
 
 Twiddle tables stay resident on the context across batches.  A request's
 result never depends on what it was batched with: every product is computed
@@ -81,10 +82,17 @@ class Request:
     arrival: float          # seconds after the start of the run
     a: np.ndarray           # uint32 coefficients
     b: np.ndarray
+    out: np.ndarray = None  # optional client buffer (uint64, >= nout words) that receives the product
     result: np.ndarray = None
     admitted: float = None
     finished: float = None
     batch: int = -1
+
+    def __post_init__(self):
+        if self.out is not None and not (isinstance(self.out, np.ndarray) and self.out.dtype == np.uint64
+                                         and self.out.ndim == 1 and self.out.size >= self.nout
+                                         and self.out.flags.c_contiguous and self.out.flags.writeable):
+            raise ValueError("out must be a writable contiguous uint64 array of at least na + nb - 1 words")
 
     @property
     def nout(self) -> int:
@@ -214,7 +222,12 @@ class PolymulServer:
             if bt.event.query():
                 def unpack(job, base=bt.host_off):
                     r, o = job
-                    r.result = self.host_np[base + o:base + o + 8 * r.nout].view(np.uint64).copy()
+                    src = self.host_np[base + o:base + o + 8 * r.nout].view(np.uint64)
+                    if r.out is not None:  # into the client's buffer: no allocation here
+                        np.copyto(r.out[:r.nout], src)
+                        r.result = r.out[:r.nout]
+                    else:
+                        r.result = src.copy()
 
                 list(self.pool.map(unpack, zip(bt.reqs, bt.out_offs)))
                 for r in bt.reqs:
@@ -293,8 +306,18 @@ class PolymulServer:
         self.host_np = None
 
 
-def make_requests(seed: int, count: int, rate_per_s: float, lo_bits: float = 10, hi_bits: float = 20):
-    """Poisson arrivals of products with log-uniform lengths (see workloads.poisson_requests)."""
+def make_requests(seed: int, count: int, rate_per_s: float, lo_bits: float = 10, hi_bits: float = 20,
+                  client_out: bool = False):
+    """Poisson arrivals of products with log-uniform lengths (see workloads.poisson_requests).
+    client_out: each request carries a result buffer that the client allocated and touched
+    beforehand (as a client reusing its buffers would have), so that the server's unpacking
+    is one copy per product and no page faults."""
     from .workloads import poisson_requests
-    return [Request(i, t, a, b) for i, (t, a, b) in enumerate(poisson_requests(seed, count, rate_per_s, lo_bits,
-                                                                              hi_bits))]
+    reqs = []
+    for i, (t, a, b) in enumerate(poisson_requests(seed, count, rate_per_s, lo_bits, hi_bits)):
+        out = None
+        if client_out:
+            out = np.empty(a.size + b.size - 1, np.uint64)
+            out.fill(0)
+        reqs.append(Request(i, t, a, b, out))
+    return reqs

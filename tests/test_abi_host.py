@@ -231,6 +231,22 @@ def test_serving_workspace_bound_covers_library_size():
         assert exact <= sum(r.workspace_bound() for r in reqs) + _GROUP_SLACK
 
 
+def test_serving_client_buffers_are_checked():
+    """A request's own result buffer must be a writable contiguous uint64 array of at least
+    na + nb - 1 words; anything else is refused when the request is made (host only)."""
+    import numpy as np
+    from paper_1205_2926_amd.serve import Request
+    a, b = np.ones(10, np.uint32), np.ones(7, np.uint32)
+    Request(0, 0.0, a, b, np.empty(16, np.uint64))
+    Request(0, 0.0, a, b, np.empty(40, np.uint64))
+    ro = np.empty(16, np.uint64)
+    ro.flags.writeable = False
+    for bad in (np.empty(15, np.uint64), np.empty(16, np.int32), np.empty((4, 4), np.uint64),
+                np.empty(32, np.uint64)[::2], ro):
+        with pytest.raises(ValueError):
+            Request(0, 0.0, a, b, bad)
+
+
 def test_bigmul_sizing_checks():
     """Large-integer plans: workspace from lengths alone, operand limits checked on the host."""
     ws = hntt.bigmul_workspace_size([(1000, 3000), (1, 1)])

@@ -72,3 +72,15 @@ def test_large_requests_up_to_2e20(ctx, orc):
     assert stats["completed"] == len(reqs)
     for r in reqs:
         _check(orc, r)
+
+
+def test_client_result_buffers(ctx, orc):
+    """Requests that bring their own result buffers get the same products, written in place."""
+    reqs = make_requests(seed=7, count=12, rate_per_s=4000.0, lo_bits=10, hi_bits=15, client_out=True)
+    ref = make_requests(seed=7, count=12, rate_per_s=4000.0, lo_bits=10, hi_bits=15)
+    PolymulServer(ctx, 64 << 20, streams=2, max_batch=4).run(reqs, time_limit=60)
+    PolymulServer(ctx, 64 << 20, streams=2, max_batch=4).run(ref, time_limit=60)
+    for r, q in zip(reqs, ref):
+        assert np.shares_memory(r.result, r.out)
+        np.testing.assert_array_equal(r.result, q.result)
+        _check(orc, r, full=r.nout < 3000)
