@@ -4,7 +4,8 @@ For a (length, word size, batch) shape it times forward+inverse transforms on
 the GPU under every legal schedule in a small search space (columns per
 workgroup in the column pass, rows per workgroup in the row pass, transforms
 per chunk) and installs the fastest one on the context with
-``Context.set_tuning``.  The GPU is kept busy for a second before the first
+``Context.set_tuning``.  ``tune_polymul`` does the same per length class of a batch of
+exact products, timing the whole batch plan.  The GPU is kept busy for a second before the first
 trial, and the six fastest candidates are timed again in turn, three times
 each, and ranked by their median.  Results are cached in a JSON file keyed by the GPU's compute-unit
 count, memory size and the shape (``$HNTT_TUNE_CACHE``, default ``~/.cache/hntt/tune.json``).  The
@@ -143,6 +144,69 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
         cache[key] = rec
         save_cache(cache)
     return rec
+
+
+def _plan_ms(plan, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        plan.execute()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_polymul(ctx, pairs, outs, plain: bool = False, reps: int = 3, verbose: bool = False,
+                 big: bool = False) -> dict:
+    """Pick and install, length class by length class, the (columns, rows) per workgroup of the
+    two-pass transforms of a batch of exact products (`Context.polymul_plan` arguments, or
+    `Context.bigmul_plan` ones with big=True), by timing the whole batch plan: its passes
+    differ from standalone transforms (zero upper halves read as zero, the fused pointwise
+    product, three primes per launch).  Candidates are the default schedule and its
+    neighbours; classes are taken largest first, each with the others fixed; one-pass
+    classes have nothing to tune."""
+    make = ctx.bigmul_plan if big else ctx.polymul_plan
+    classes = sorted({max(1, (max(a.numel(), b.numel()) - 1).bit_length() + 1) for a, b in pairs}, reverse=True)
+    chosen = {}
+    t0 = time.time()
+    plan = make(pairs, outs, plain=plain)
+    for _ in range(10):  # warm the GPU
+        plan.execute()
+    plan.destroy()
+    for l in classes:
+        ctx.set_tuning(l, 32, 0, 0, 0)
+        default = ctx.get_plan(l, 32)
+        if not default["g_cols"]:
+            continue  # one pass
+        # the default and its neighbours: a quarter, half and twice its columns or rows
+        # per workgroup (the library refuses those that do not fit)
+        cands = []
+        for gc in (default["g_cols"] // 4, default["g_cols"] // 2, default["g_cols"], default["g_cols"] * 2):
+            for gr in (default["g_rows"] // 4, default["g_rows"] // 2, default["g_rows"], default["g_rows"] * 2):
+                if gc < 1 or gr < 1 or (gc, gr) in cands:
+                    continue
+                try:
+                    ctx.set_tuning(l, 32, gc, gr, 0)
+                except hntt.HnttError:
+                    continue
+                cands.append((gc, gr))
+        times = {}
+        for rnd in range(2):  # all once, then the three fastest again
+            pool = cands if rnd == 0 else sorted(cands, key=lambda c: statistics.median(times[c]))[:3]
+            for gc, gr in pool:
+                ctx.set_tuning(l, 32, gc, gr, 0)
+                plan = make(pairs, outs, plain=plain)
+                plan.execute()
+                times.setdefault((gc, gr), []).append(_plan_ms(plan, reps))
+                plan.destroy()
+        best = min(times, key=lambda c: statistics.median(times[c]))
+        ctx.set_tuning(l, 32, best[0], best[1], 0)
+        chosen[l] = {"g_cols": best[0], "g_rows": best[1], "ms": statistics.median(times[best]),
+                     "default": {"g_cols": default["g_cols"], "g_rows": default["g_rows"]}}
+        if verbose:
+            print(f"  class 2^{l}: {chosen[l]}", flush=True)
+    return {"classes": chosen, "tune_s": time.time() - t0}
 
 
 def main():

@@ -99,12 +99,17 @@ def polymul(args):
         words += 1 << l
     res = {}
     for plain in (False, True):
+        # each policy gets its own per-class schedules, timed on this batch's own plan
+        tuned = autotune.tune_polymul(ctx, dpairs, outs, plain=plain)
         plan = ctx.polymul_plan(dpairs, outs, plain=plain)
         plan.execute()
         torch.cuda.synchronize()
         ms = _events_ms(plan.execute, max(3, args.steps // 2))
         res["plain" if plain else "lazy"] = {"ms_per_batch": ms, "products_per_s": len(pairs) / (ms / 1e3),
-                                             "butterflies_per_s": bfly / (ms / 1e3)}
+                                             "butterflies_per_s": bfly / (ms / 1e3),
+                                             "schedules": {f"2^{l}": {k: v[k] for k in ("g_cols", "g_rows")}
+                                                           for l, v in tuned["classes"].items()},
+                                             "tune_s": tuned["tune_s"]}
         plan.destroy()
     orc = oracle.Oracle()
     rr = random.Random(7)
@@ -193,11 +198,14 @@ def bigmul(args):
     outs = [torch.empty(2 * n, dtype=torch.int32, device="cuda") for _ in range(count)]
     res = {}
     for policy in ("lazy", "plain"):
+        tuned = autotune.tune_polymul(ctx, dpairs, outs, plain=policy == "plain", big=True)
         plan = ctx.bigmul_plan(dpairs, outs, plain=policy == "plain")
         plan.execute()
         torch.cuda.synchronize()
         ms = _events_ms(plan.execute, max(3, args.steps // 2))
-        res[policy] = {"ms_per_batch": ms, "products_per_s": count / (ms / 1e3)}
+        res[policy] = {"ms_per_batch": ms, "products_per_s": count / (ms / 1e3),
+                       "schedules": {f"2^{l}": {k: v[k] for k in ("g_cols", "g_rows")}
+                                     for l, v in tuned["classes"].items()}}
         plan.destroy()
     got = [o.cpu().numpy().view(np.uint32) for o in outs]
     for i in (0, count - 1):
