@@ -28,7 +28,7 @@ from . import hntt
 
 CACHE = os.environ.get("HNTT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hntt", "tune.json"))
 REFINE_TOP, REFINE_ROUNDS = 6, 3
-SPACE = {"g_cols": [4, 8, 16], "g_rows": [1, 2, 4, 8, 16], "batch_chunk": [8, 16, 32, 64]}
+SPACE = {"g_cols": [4, 8, 16, 32, 64], "g_rows": [1, 2, 4, 8, 16, 32, 64], "batch_chunk": [8, 16, 32, 64]}
 
 
 def _key(log2_len, word_bits, batch, policy):
