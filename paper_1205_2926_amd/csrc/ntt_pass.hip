@@ -62,6 +62,7 @@ using Wd = Word64;
 #endif
 using T = typename Wd::T;
 constexpr bool kInverse = HNTT_INVERSE != 0;
+constexpr int kRowPadShift = row_pad_shift(HNTT_WORD);
 
 // Global (HBM) address space: lets the compiler emit global_* instead of flat_*
 // memory instructions, which would also count against the LDS wait counter.
@@ -275,9 +276,7 @@ __device__ __forceinline__ T reduce_final(T x, T p) {
 struct KernelArgs {
   BatchPtrs ptrs;             // transforms (slot 0) when `table` is null
   const XformEntry *table;    // else: device table of (pointer, prime slot)
-  int nbatch;
-  int units;                  // tiles per transform
-  int total_tiles;            // nbatch * units
+  int units;                  // tiles per transform (the grid is units x transforms)
   int log_other;              // rows: log2(#rows); cols: log2(#columns)
   int group;                  // G
   int normalize;              // reduce the final output to [0,p)
@@ -440,8 +439,8 @@ struct GlobalIO {
 
 // LDS side.  Columns: element (g, pos) at pad1(pos) * G + g, one pad word per 32
 // positions, so both rounds' access patterns hit distinct banks.  Rows: element
-// (g, pos) at g * pitch + pad4(pos), four pad words per 32 positions, which keeps
-// 16-byte alignment of each group of 4 for vector accesses of the low round.
+// (g, pos) at g * pitch + pos + 4 (pos >> S) (row_pad_shift), which keeps the
+// 16-byte alignment of vector accesses.
 template <bool Cols>
 struct LdsIO {
   static constexpr bool kContig = !Cols;
@@ -449,7 +448,7 @@ struct LdsIO {
   int G, g, pitch;
   __device__ __forceinline__ int idx(int pos) const {
     if constexpr (Cols) return (pos + (pos >> 5)) * G + g;
-    else return g * pitch + pos + ((pos >> 5) << 2);
+    else return g * pitch + pos + ((pos >> kRowPadShift) << 2);
   }
   __device__ __forceinline__ T load2(int lp, int up) const { return tile[idx(lp + up)]; }
   __device__ __forceinline__ void store2(int lp, int up, T x) const { tile[idx(lp + up)] = x; }
@@ -511,7 +510,7 @@ struct TwStage {
 // Padded LDS words per sub-transform (rows: row pitch; cols: rows of the tile).
 template <bool Cols>
 constexpr int padded_len(int N) {
-  return Cols ? N + N / 32 : N + (N >= 32 ? N / 8 : 0);
+  return Cols ? N + N / 32 : (int)row_padded_len((size_t)N, HNTT_WORD);
 }
 
 template <int Pol, bool Cols, int KH, int KM, int KL, bool TT>
@@ -641,7 +640,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
             for (int j = 0; j < kLoad; ++j) {
               const int i = threadIdx.x + j * nthr;
               const int row = i / kCh, c = (i % kCh) * kVec;
-              *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2)) = q[j];
+              *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> kRowPadShift) << 2)) = q[j];
             }
             stage.store(tws, twg);
             __syncthreads();  // tile and twiddle table staged
@@ -693,7 +692,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           for (int j = 0; j < kPer; ++j) {
             const int i = threadIdx.x + j * nthr;
             const int row = i / kChunks, c = (i % kChunks) * kVec;
-            const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2));
+            const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + row * kPitch + c + ((c >> kRowPadShift) << 2));
             const T *w = reinterpret_cast<const T *>(&q);
             T *wo = reinterpret_cast<T *>(&o[j]);
 #pragma unroll
@@ -850,9 +849,7 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   HNTT_NS::KernelArgs a{};
   a.ptrs = ptrs;
   a.table = pp.table;
-  a.nbatch = pp.nbatch;
   a.units = units;
-  a.total_tiles = (int)total;
   a.log_other = log_other;
   a.group = pp.group;
   a.normalize = pp.normalize ? 1 : 0;
