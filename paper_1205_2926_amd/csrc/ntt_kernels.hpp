@@ -79,12 +79,12 @@ inline RoundSplit pass_split(int n, int word_bits, bool whole = false) {
   if (n == 10) return {4, 3, 3};
   return {4, 4, n - 8};
 }
-// Row tiles in LDS: four pad words after every 2^S words of a row, S = 6 for
-// 32-bit words and 5 for 64-bit ones.  Consecutive threads of the low round
-// (16-byte vector accesses, 2^KL words apart) and consecutive 16-byte chunks of
-// the copy in or out of the tile then fall in distinct banks.
-constexpr int row_pad_shift(int word_bits) { return word_bits == 32 ? 6 : 5; }
-constexpr size_t row_padded_len(size_t N, int word_bits) { return N + (N >> row_pad_shift(word_bits)) * 4; }
+// Row tiles in LDS: four pad words after every 32 words of a row, so that
+// consecutive threads of the low round (16-byte vector accesses, 2^KL words
+// apart) fall in distinct banks.  (One pad per 64 words instead, which would
+// also spare the copy out of the tile its few two-way conflicts, put conflicts
+// into the low round: three times the conflict cycles, measured.)
+constexpr size_t row_padded_len(size_t N) { return N + (N >> 5) * 4; }
 
 // Threads per sub-transform: one group of the largest round each.
 inline int pass_tpt(int n, int word_bits, bool whole = false) {

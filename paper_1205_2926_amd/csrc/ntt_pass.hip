@@ -62,7 +62,6 @@ using Wd = Word64;
 #endif
 using T = typename Wd::T;
 constexpr bool kInverse = HNTT_INVERSE != 0;
-constexpr int kRowPadShift = row_pad_shift(HNTT_WORD);
 
 // Global (HBM) address space: lets the compiler emit global_* instead of flat_*
 // memory instructions, which would also count against the LDS wait counter.
@@ -439,7 +438,7 @@ struct GlobalIO {
 
 // LDS side.  Columns: element (g, pos) at pad1(pos) * G + g, one pad word per 32
 // positions, so both rounds' access patterns hit distinct banks.  Rows: element
-// (g, pos) at g * pitch + pos + 4 (pos >> S) (row_pad_shift), which keeps the
+// (g, pos) at g * pitch + pos + 4 (pos >> 5) (row_padded_len), which keeps the
 // 16-byte alignment of vector accesses.
 template <bool Cols>
 struct LdsIO {
@@ -448,7 +447,7 @@ struct LdsIO {
   int G, g, pitch;
   __device__ __forceinline__ int idx(int pos) const {
     if constexpr (Cols) return (pos + (pos >> 5)) * G + g;
-    else return g * pitch + pos + ((pos >> kRowPadShift) << 2);
+    else return g * pitch + pos + ((pos >> 5) << 2);
   }
   __device__ __forceinline__ T load2(int lp, int up) const { return tile[idx(lp + up)]; }
   __device__ __forceinline__ void store2(int lp, int up, T x) const { tile[idx(lp + up)] = x; }
@@ -510,7 +509,7 @@ struct TwStage {
 // Padded LDS words per sub-transform (rows: row pitch; cols: rows of the tile).
 template <bool Cols>
 constexpr int padded_len(int N) {
-  return Cols ? N + N / 32 : (int)row_padded_len((size_t)N, HNTT_WORD);
+  return Cols ? N + N / 32 : (int)row_padded_len((size_t)N);
 }
 
 template <int Pol, bool Cols, int KH, int KM, int KL, bool TT>
@@ -640,7 +639,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
             for (int j = 0; j < kLoad; ++j) {
               const int i = threadIdx.x + j * nthr;
               const int row = i / kCh, c = (i % kCh) * kVec;
-              *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> kRowPadShift) << 2)) = q[j];
+              *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2)) = q[j];
             }
             stage.store(tws, twg);
             __syncthreads();  // tile and twiddle table staged
@@ -692,7 +691,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           for (int j = 0; j < kPer; ++j) {
             const int i = threadIdx.x + j * nthr;
             const int row = i / kChunks, c = (i % kChunks) * kVec;
-            const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + row * kPitch + c + ((c >> kRowPadShift) << 2));
+            const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2));
             const T *w = reinterpret_cast<const T *>(&q);
             T *wo = reinterpret_cast<T *>(&o[j]);
 #pragma unroll
