@@ -190,6 +190,12 @@ def main():
         schedules[policy] = ctx.get_plan(l, cfg.word_bits)
         sec, kernels = time_steps(ctx, x, p, w, policy, args.steps, args.warmup)
         res[policy] = (sec, kernels)
+    # the other policies once more under the lazy schedule: the butterflies alone compared
+    same = {}
+    sched = schedules["lazy"]
+    ctx.set_tuning(l, cfg.word_bits, sched["g_cols"], sched["g_rows"], sched["batch_chunk"])
+    for policy in policies[1:]:
+        same[policy] = time_steps(ctx, x, p, w, policy, args.steps, args.warmup)[0]
     assert np.array_equal(x.cpu().numpy().view(np.uint32), x_np), "data changed across steps"
 
     sec, kernels = res["lazy"]
@@ -235,6 +241,7 @@ def main():
             out[other] = {"value": bfly_step / psec, "ms_per_step": psec * 1e3, "schedule": schedules[other],
                           "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in pk.items()}}
             out[f"lazy_over_{other}"] = psec / sec
+            out[f"lazy_over_{other}_same_schedule"] = same[other] / sec
     if not args.no_cpu_baseline:
         cb, fwd, rows = cpu_baseline(cfg, w, x_np, args.cpu_sample)
         assert np.array_equal(fwd[0], fwd0.astype(np.uint64)), "GPU forward differs from the oracle"
