@@ -115,39 +115,19 @@ __device__ __forceinline__ void garner_words(const PolyArgs &args, const uint32_
 enum : uint32_t { kKill = 0, kGen = 1, kProp = 2 };
 
 constexpr int kPerThread = kChunk / kThreads;  // consecutive limbs per thread
+static_assert(kPerThread == 4, "a thread's limbs are stored as one 16-byte vector");
 
+// The three words of the exact coefficients of one product (written over B_1, B_2,
+// B_3) and its lengths: s_k = w0[k] + w1[k-1] + w2[k-2] for k < nlimb.
 struct BigView {
   const uint32_t *w0, *w1, *w2;
   uint32_t nout, nlimb;
-  __device__ __forceinline__ uint64_t s(int64_t k) const {  // s_k (0 outside the product)
-    if (k < 0 || k >= (int64_t)nlimb) return 0;
-    uint64_t v = 0;
-    if (k < (int64_t)nout) v += w0[k];
-    if (k >= 1 && k - 1 < (int64_t)nout) v += w1[k - 1];
-    if (k >= 2 && k - 2 < (int64_t)nout) v += w2[k - 2];
-    return v;
-  }
 };
 
 __device__ __forceinline__ BigView big_view(const PolyArgs &args, const PolyPair &pp) {
   const uint32_t L = 1u << pp.log2_len;
   const uint32_t *ws = args.workspace + pp.ws_off;
   return BigView{ws + (size_t)L, ws + 3 * (size_t)L, ws + 5 * (size_t)L, pp.na + pp.nb - 1, pp.na + pp.nb};
-}
-
-// t_k and the states of this thread's kPerThread limbs starting at k0.
-__device__ __forceinline__ void big_states(const BigView &v, int64_t k0, uint64_t *t, uint32_t *st) {
-  uint64_t prev = v.s(k0 - 1);
-#pragma unroll
-  for (int i = 0; i < kPerThread; ++i) {
-    const uint64_t cur = v.s(k0 + i);
-    t[i] = (cur & 0xFFFFFFFFull) + (prev >> 32);
-    st[i] = (k0 + i >= (int64_t)v.nlimb) ? kProp
-            : t[i] >= (1ull << 32)       ? kGen
-            : t[i] == 0xFFFFFFFFull      ? kProp
-                                         : kKill;
-    prev = cur;
-  }
 }
 
 __device__ __forceinline__ uint32_t fold(uint32_t left, uint32_t right) { return right == kProp ? left : right; }
@@ -249,27 +229,62 @@ __global__ void __launch_bounds__(kThreads) k_big_chunk_carry(PolyArgs args) {
   }
 }
 
+// The chunk's words are first copied into LDS with coalesced loads (each thread's
+// four consecutive limbs would otherwise read every word four lanes apart), and
+// each thread stores its four limbs as one 16-byte vector.
 __global__ void __launch_bounds__(kThreads) k_big_apply(PolyArgs args) {
+  constexpr int kHalo = 3;
+  __shared__ uint32_t W[3][kChunk + kHalo];
   __shared__ uint32_t lds[kThreads / 64];
   for (int c = blockIdx.x; c < args.nchunks_out; c += gridDim.x) {
     const ChunkEntry ce = args.chunks_out[c];
     const PolyPair pp = args.pairs[ce.pair];
     const BigView v = big_view(args, pp);
+    const int64_t j0 = (int64_t)ce.start - kHalo;  // coefficient of LDS entry 0
+    for (int i = threadIdx.x; i < kChunk + kHalo; i += kThreads) {
+      const int64_t j = j0 + i;
+      const bool in = j >= 0 && j < (int64_t)v.nout;
+      W[0][i] = in ? v.w0[j] : 0u;
+      W[1][i] = in ? v.w1[j] : 0u;
+      W[2][i] = in ? v.w2[j] : 0u;
+    }
+    __syncthreads();
+    auto s_at = [&](int64_t k) -> uint64_t {  // s_k from LDS, 0 outside the product
+      if (k < 0 || k >= (int64_t)v.nlimb) return 0;
+      const int i = (int)(k - j0);
+      return (uint64_t)W[0][i] + W[1][i - 1] + W[2][i - 2];
+    };
     const int64_t k0 = (int64_t)ce.start + threadIdx.x * kPerThread;
     uint64_t t[kPerThread];
-    uint32_t st[kPerThread];
-    big_states(v, k0, t, st);
     uint32_t mine = kProp;
+    uint64_t prev = s_at(k0 - 1);
 #pragma unroll
-    for (int i = 0; i < kPerThread; ++i) mine = fold(mine, st[i]);
+    for (int i = 0; i < kPerThread; ++i) {
+      const uint64_t cur = s_at(k0 + i);
+      t[i] = (cur & 0xFFFFFFFFull) + (prev >> 32);
+      const uint32_t st = (k0 + i >= (int64_t)v.nlimb) ? kProp
+                          : t[i] >= (1ull << 32)       ? kGen
+                          : t[i] == 0xFFFFFFFFull      ? kProp
+                                                       : kKill;
+      mine = fold(mine, st);
+      prev = cur;
+    }
     uint32_t all;
-    uint32_t carry = wg_carry_in(mine, args.chunk_carry[c], lds, &all);
-    uint32_t *out = static_cast<uint32_t *>(pp.out);
+    uint32_t carry = wg_carry_in(mine, args.chunk_carry[c], lds, &all);  // ends with a barrier
+    uint32_t o[kPerThread];
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
       const uint64_t x = t[i] + carry;
-      if (k0 + i < (int64_t)v.nlimb) out[k0 + i] = (uint32_t)x;
+      o[i] = (uint32_t)x;
       carry = (uint32_t)(x >> 32);
+    }
+    uint32_t *out = static_cast<uint32_t *>(pp.out) + k0;
+    if (k0 + kPerThread <= (int64_t)v.nlimb && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+      *reinterpret_cast<uint4 *>(out) = make_uint4(o[0], o[1], o[2], o[3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kPerThread; ++i)
+        if (k0 + i < (int64_t)v.nlimb) out[i] = o[i];
     }
   }
 }
