@@ -62,6 +62,11 @@ using Wd = Word64;
 #endif
 using T = typename Wd::T;
 constexpr bool kInverse = HNTT_INVERSE != 0;
+// 64-bit words read the twiddles of their high and middle rounds from global
+// memory (L1/L2) instead of an LDS copy: the copy (16 bytes per entry) would
+// take a third of the LDS that a tile of 2^11 words leaves, and halve the
+// workgroups a CU holds.
+constexpr bool kTwGlobal = HNTT_WORD == 64;
 
 // Global (HBM) address space: lets the compiler emit global_* instead of flat_*
 // memory instructions, which would also count against the LDS wait counter.
@@ -249,7 +254,8 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
         } else {
           const int b = b_lo + hb;
           const int pos = base | (e << b_lo);
-          const TwT<Pol> tw = tws[(1 << b) + (pos & ((1 << b) - 1))];
+          const int ti = (1 << b) + (pos & ((1 << b) - 1));
+          const TwT<Pol> tw = kTwGlobal ? twg[ti] : tws[ti];
           bfly<Pol>(v[e], v[e | (1 << hb)], tw, m);
         }
       }
@@ -490,6 +496,7 @@ struct TwStage {
   TwT<Pol> r[kR];
   int nthr;  // threads in the workgroup
   __device__ __forceinline__ void load(const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) {
+    if constexpr (kTwGlobal) return;
 #pragma unroll
     for (int j = 0; j < kR; ++j) {
       const int i = threadIdx.x + j * nthr;
@@ -497,6 +504,7 @@ struct TwStage {
     }
   }
   __device__ __forceinline__ void store(TwT<Pol> *tws, const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) const {
+    if constexpr (kTwGlobal) return;
 #pragma unroll
     for (int j = 0; j < kR; ++j) {
       const int i = threadIdx.x + j * nthr;
@@ -534,7 +542,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   }
   const size_t C = (size_t)1 << a.log_other;
   TwT<Pol> *tws = reinterpret_cast<TwT<Pol> *>(smem_raw);
-  T *tile = reinterpret_cast<T *>(tws + N);
+  T *tile = kTwGlobal ? reinterpret_cast<T *>(smem_raw) : reinterpret_cast<T *>(tws + N);
 
   // One tile (transform b, unit) per workgroup.  Blocks are dealt to the 8 XCDs
   // round-robin; each XCD takes a contiguous eighth of the units for every transform,
