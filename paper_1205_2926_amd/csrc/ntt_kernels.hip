@@ -88,8 +88,8 @@ size_t pass_lds_bytes(const PassParams &pp) {
   const size_t N = (size_t)1 << pp.n;
   // per-stage twiddle table (N pairs) + padded tile (see LdsIO in ntt_pass.hip)
   const size_t padded = pp.kind == PassKind::kCols ? N + N / 32 : row_padded_len(N);
-  // (64-bit words keep no LDS copy of the twiddle table: see kTwGlobal in ntt_pass.hip)
-  const size_t bytes = wb * ((pp.word_bits == 64 ? 0 : 2 * N) + padded * pp.group);
+  // (no LDS copy of the twiddle table where tw_global says so)
+  const size_t bytes = wb * ((tw_global(pp.n, pp.word_bits) ? 0 : 2 * N) + padded * pp.group);
   return bytes <= 160 * 1024 ? bytes : 0;
 }
 

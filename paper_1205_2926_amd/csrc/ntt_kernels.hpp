@@ -86,6 +86,14 @@ inline RoundSplit pass_split(int n, int word_bits, bool whole = false) {
 // into the low round: three times the conflict cycles, measured.)
 constexpr size_t row_padded_len(size_t N) { return N + (N >> 5) * 4; }
 
+// Whether the rounds of a pass over 2^n-word sub-transforms that do not have
+// compile-time twiddles read them from global memory (L1/L2) instead of an LDS
+// copy of the table.  For 64-bit words the copy (16-byte entries: a third of
+// the LDS next to a 2^11-word tile) would cost a workgroup per CU; for 32-bit
+// words the LDS copy is faster at every length (measured on the 4096-product
+// batch, whose passes are 2^6 to 2^9 words: 4-6% slower from memory).
+constexpr bool tw_global(int n, int word_bits) { return (void)n, word_bits == 64; }
+
 // Threads per sub-transform: one group of the largest round each.
 inline int pass_tpt(int n, int word_bits, bool whole = false) {
   const RoundSplit r = pass_split(n, word_bits, whole);

@@ -62,11 +62,9 @@ using Wd = Word64;
 #endif
 using T = typename Wd::T;
 constexpr bool kInverse = HNTT_INVERSE != 0;
-// 64-bit words read the twiddles of their high and middle rounds from global
-// memory (L1/L2) instead of an LDS copy: the copy (16 bytes per entry) would
-// take a third of the LDS that a tile of 2^11 words leaves, and halve the
-// workgroups a CU holds.
-constexpr bool kTwGlobal = HNTT_WORD == 64;
+// Sub-transforms whose high and middle rounds read their twiddles from global
+// memory (L1/L2) instead of an LDS copy (tw_global in ntt_kernels.hpp).
+constexpr bool tw_global_here(int n) { return tw_global(n, HNTT_WORD); }
 
 // Global (HBM) address space: lets the compiler emit global_* instead of flat_*
 // memory instructions, which would also count against the LDS wait counter.
@@ -255,7 +253,7 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
           const int b = b_lo + hb;
           const int pos = base | (e << b_lo);
           const int ti = (1 << b) + (pos & ((1 << b) - 1));
-          const TwT<Pol> tw = kTwGlobal ? twg[ti] : tws[ti];
+          const TwT<Pol> tw = tw_global_here(N_LOG) ? twg[ti] : tws[ti];
           bfly<Pol>(v[e], v[e | (1 << hb)], tw, m);
         }
       }
@@ -492,11 +490,12 @@ struct LdsEdgeIO {
 // thread into registers, store() writes them to LDS (and copies any remainder).
 template <int Pol, int N>
 struct TwStage {
+  static constexpr int N_LOG2 = __builtin_ctz(N);
   static constexpr int kR = 8;
   TwT<Pol> r[kR];
   int nthr;  // threads in the workgroup
   __device__ __forceinline__ void load(const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) {
-    if constexpr (kTwGlobal) return;
+    if constexpr (tw_global_here(N_LOG2)) return;
 #pragma unroll
     for (int j = 0; j < kR; ++j) {
       const int i = threadIdx.x + j * nthr;
@@ -504,7 +503,7 @@ struct TwStage {
     }
   }
   __device__ __forceinline__ void store(TwT<Pol> *tws, const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) const {
-    if constexpr (kTwGlobal) return;
+    if constexpr (tw_global_here(N_LOG2)) return;
 #pragma unroll
     for (int j = 0; j < kR; ++j) {
       const int i = threadIdx.x + j * nthr;
@@ -542,7 +541,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   }
   const size_t C = (size_t)1 << a.log_other;
   TwT<Pol> *tws = reinterpret_cast<TwT<Pol> *>(smem_raw);
-  T *tile = kTwGlobal ? reinterpret_cast<T *>(smem_raw) : reinterpret_cast<T *>(tws + N);
+  T *tile = tw_global_here(N_LOG) ? reinterpret_cast<T *>(smem_raw) : reinterpret_cast<T *>(tws + N);
 
   // One tile (transform b, unit) per workgroup.  Blocks are dealt to the 8 XCDs
   // round-robin; each XCD takes a contiguous eighth of the units for every transform,
