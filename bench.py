@@ -9,10 +9,14 @@ again with the fully reducing (plain) butterflies of Algorithm 2 and with the
 Montgomery butterflies of Algorithm 5 under the same kernel template.
 
 Reported: butterflies/s (batch * l * L/2 per direction, counted as the paper
-does), the roofline of the dominant kernel (HIP-event durations of the launches
-inside the timed region), the compulsory-byte HBM fraction, the lazy/plain and
-lazy/Montgomery ratios, and the CPU oracle timed on a bounded sample on the host cores.
-Prints one JSON line.
+does) for the round trip and for each direction (median, min and max over the
+steps), the roofline of the dominant kernel (HIP-event durations of the launches
+inside the timed region), the HBM fraction read two ways (compulsory bytes, and
+the bytes the rocprofv3 counters recorded) against both the 8 TB/s peak and a
+plain device copy measured in the same process, the VALU issue rate of the
+dominant kernel, the lazy/plain and lazy/Montgomery ratios, and the CPU oracle
+timed on a bounded sample on the host cores (batch-parallel, and one transform
+on one thread).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -66,6 +70,51 @@ def copy_calibration():
                       "launches": 3}))
 
 
+def copy_bandwidth(reps: int = 10) -> float:
+    """GB/s of a plain 1 GiB device-to-device copy (bytes read + bytes written over the
+    median launch time): the practical HBM ceiling next to the 8 TB/s peak."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        dst.copy_(src)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))[reps // 2]
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def direction_times(ctx, x, p, w, policy, steps):
+    """Per-step forward, inverse and round-trip times (ms) from events on the stream the
+    library launches on (torch's current stream), in a run of its own."""
+    import torch
+    kw = {"plain": policy == "plain", "mont": policy == "mont"}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        ctx.ntt_forward(x, p, w, **kw)
+        ev[2 * i + 1].record()
+        ctx.ntt_inverse(x, p, w, **kw)
+        ev[2 * i + 2].record()
+    torch.cuda.synchronize()
+    fwd = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
+    inv = [ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(steps)]
+    return {"forward": fwd, "inverse": inv, "round_trip": [a + b for a, b in zip(fwd, inv)]}
+
+
+def summarize_ms(ms, bfly):
+    import statistics
+    med = statistics.median(ms)
+    return {"butterflies_per_s": bfly / (med * 1e-3), "median_ms": med, "min_ms": min(ms), "max_ms": max(ms)}
+
+
 def pass_butterflies(name: str, batch: int, l: int) -> int:
     """Radix-2 butterflies in one launch of the named pass (kernel name ends in _n<log2 sub-length>)."""
     n = int(name.rsplit("_n", 1)[1])
@@ -102,9 +151,10 @@ def time_steps(ctx, x, p, w, policy, steps, warmup):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_64x2^20_u32.json")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte counters, or None when
-    the kernel sources changed since the counters were taken."""
+def measured_counter(kernel: str, field: str = "bytes_per_launch"):
+    """A per-launch figure for `kernel` from the committed rocprofv3 counters (HBM bytes, or VALU
+    wave instructions with field="valu_insts_per_launch"), or None when the kernel sources
+    changed since the counters were taken."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
@@ -115,7 +165,7 @@ def measured_traffic(kernel: str):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != rec["source_sha256"]:
         return None
-    return rec["bytes_per_launch"].get(kernel)
+    return rec.get(field, {}).get(kernel)
 
 
 def cpu_baseline(cfg, w, x_np, sample):
@@ -132,6 +182,10 @@ def cpu_baseline(cfg, w, x_np, sample):
         orc.lib.oracle_ntt_inverse(oracle._ptr(a), l, p, w)
         return f
 
+    one = rows[0].copy()
+    t0 = time.perf_counter()
+    work(one)
+    single = time.perf_counter() - t0
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
         fwd = list(ex.map(work, rows))
@@ -139,7 +193,20 @@ def cpu_baseline(cfg, w, x_np, sample):
     bfly = sample * 2 * l * (1 << (l - 1))
     return {"value": bfly / wall, "unit": "butterflies/s", "cores": cores, "kind": "oracle",
             "sample": f"{sample} of the 64 transforms (length 2^20), forward + inverse, one transform per "
-                      f"thread, {cores} threads, {wall:.2f} s wall", "wall_s": wall}, fwd, rows
+                      f"thread, {cores} threads, {wall:.2f} s wall", "wall_s": wall,
+            "single_thread": {"value": 2 * l * (1 << (l - 1)) / single, "unit": "butterflies/s",
+                              "sample": "one transform, forward + inverse, on one thread", "wall_s": single},
+            "cpu_model": cpu_model()}, fwd, rows
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -178,6 +245,7 @@ def main():
     assert np.array_equal(x.cpu().numpy().view(np.uint32), x_np), "round trip mismatch"
 
     bfly_step = 2 * cfg.butterflies
+    copy_gbs = copy_bandwidth()
     res = {}
     schedules = {}
     from paper_1205_2926_amd import autotune
@@ -196,6 +264,8 @@ def main():
     ctx.set_tuning(l, cfg.word_bits, sched["g_cols"], sched["g_rows"], sched["batch_chunk"])
     for policy in policies[1:]:
         same[policy] = time_steps(ctx, x, p, w, policy, args.steps, args.warmup)[0]
+    # forward and inverse apart, per step, under the lazy schedule
+    dirs = direction_times(ctx, x, p, w, "lazy", args.steps)
     assert np.array_equal(x.cpu().numpy().view(np.uint32), x_np), "data changed across steps"
 
     sec, kernels = res["lazy"]
@@ -211,9 +281,26 @@ def main():
     for r in (hbm, alu):
         r["frac"] = r["achieved"] / r["peak"]
     roof = dict(max((hbm, alu), key=lambda r: r["frac"]))
-    roof.update({"kernel": dom, "avg_launch_ms": avg_s * 1e3, "traffic": measured_traffic(dom),
+    roof.update({"kernel": dom, "avg_launch_ms": avg_s * 1e3, "traffic": measured_counter(dom),
                  "algorithmic_bytes": bytes_alg, "algorithmic_ops": ops_alg,
                  "other": (alu if roof["bound"] == "hbm" else hbm)})
+
+    # HBM read two ways (compulsory bytes; bytes the rocprofv3 counters recorded for these
+    # kernels), each against the 8 TB/s peak and against the copy measured above
+    step_bytes = {"compulsory": 2 * bytes_alg}
+    per_launch = {k: measured_counter(k) for k in kernels}
+    step_bytes["measured"] = (None if None in per_launch.values() else
+                              sum(per_launch[k] * v["launches"] for k, v in kernels.items()) / args.steps)
+    hbm_read = {"copy_GBs": copy_gbs, "peak_GBs": HBM_PEAK_GBS}
+    for kind, b in step_bytes.items():
+        hbm_read[kind] = None if b is None else {
+            "bytes_per_step": b, "GBs": b / sec / 1e9,
+            "frac_of_peak": b / sec / 1e9 / HBM_PEAK_GBS, "frac_of_copy": b / sec / 1e9 / copy_gbs}
+    insts = measured_counter(dom, "valu_insts_per_launch")
+    valu = {"kernel": dom, "wave_insts_per_launch": insts,
+            "issue_frac": None if insts is None else insts / (256 * 2.4e9 * avg_s),
+            "definition": "wave64 VALU instructions (SQ_INSTS_VALU) / (256 CUs x 1 per clock x 2.4 GHz "
+                          "x average launch time)"}
 
     out = {
         "metric": "NTT butterflies/s + %HBM roofline (L=2^20x64, 30-bit p), lazy vs plain",
@@ -232,6 +319,10 @@ def main():
                    "batch": cfg.batch, "log2_len": l, "p": p, "omega": w, "word_bits": cfg.word_bits},
         "roofline": roof,
         "hbm_frac_compulsory": (2 * bytes_alg) / sec / 1e9 / HBM_PEAK_GBS,
+        "hbm": hbm_read,
+        "valu": valu,
+        "directions": {k: summarize_ms(v, cfg.butterflies * (2 if k == "round_trip" else 1))
+                       for k, v in dirs.items()},
         "kernels_ms": {k: v["total_ms"] / v["launches"] for k, v in kernels.items()},
         "schedule": schedules.get("lazy"),
     }

@@ -1,0 +1,59 @@
+"""Host-side logic of bench.py: the one-GPU rule, the committed counter record and the
+summaries it prints (no GPU needed)."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_pass_butterflies(bench):
+    # a ten-stage pass over 64 transforms of length 2^20 runs 64 * 10 * 2^19 butterflies
+    assert bench.pass_butterflies("cols_inv_lazy_u32_n10", 64, 20) == 64 * 10 * (1 << 19)
+
+
+def test_summaries_use_the_median(bench):
+    s = bench.summarize_ms([3.0, 1.0, 2.0], 1000)
+    assert (s["median_ms"], s["min_ms"], s["max_ms"]) == (2.0, 1.0, 3.0)
+    assert s["butterflies_per_s"] == pytest.approx(1000 / 2e-3)
+
+
+def test_counter_record_matches_the_kernel_sources(bench):
+    # the committed rocprofv3 record is only used while the sources it was taken on are unchanged
+    for k in ("cols_fwd_lazy_u32_n10", "cols_inv_lazy_u32_n10", "rows_fwd_lazy_u32_n10", "rows_inv_lazy_u32_n10"):
+        b = bench.measured_counter(k)
+        v = bench.measured_counter(k, "valu_insts_per_launch")
+        if b is None:
+            pytest.skip("kernel sources changed since the counters were taken")
+        # at least the compulsory bytes (read and write 64 x 2^20 words of 4 bytes)
+        assert b >= 2 * 4 * 64 * (1 << 20)
+        assert v > 0
+    assert bench.measured_counter("no_such_kernel") is None
+
+
+def test_counter_record_is_dropped_when_sources_change(bench, tmp_path, monkeypatch):
+    import json
+    rec = json.load(open(bench.TRAFFIC_FILE))
+    rec["source_sha256"] = "0" * 64
+    f = tmp_path / "rec.json"
+    f.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_counter("cols_inv_lazy_u32_n10") is None
