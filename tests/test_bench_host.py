@@ -57,3 +57,25 @@ def test_counter_record_is_dropped_when_sources_change(bench, tmp_path, monkeypa
     f.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.measured_counter("cols_inv_lazy_u32_n10") is None
+
+
+def test_workload_product_check_accepts_products_and_rejects_corruption():
+    # the check the workload benchmarks run on GPU results, exercised here on the oracle's
+    # schoolbook products (one short enough for the exact comparison, one long one)
+    import numpy as np
+    import oracle
+    from paper_1205_2926_amd import bench_workloads as bw
+    orc = oracle.Oracle()
+    rng = np.random.Generator(np.random.PCG64(21))
+    short = (rng.integers(0, 1 << 20, 300).astype(np.uint32), rng.integers(0, 1 << 20, 200).astype(np.uint32))
+    long_ = (rng.integers(0, 1 << 20, 9000).astype(np.uint32), rng.integers(0, 1 << 20, 5000).astype(np.uint32))
+    cases = [(short, orc.schoolbook(*short)),
+             (long_, orc.schoolbook(*long_))]
+    for (a, b), c in cases:
+        c = np.asarray(c, dtype=np.uint64)
+        assert bw._product_ok(a, b, c)
+        for k in (0, c.size // 2, c.size - 1):
+            bad = c.copy()
+            bad[k] += np.uint64(1)
+            assert not bw._product_ok(a, b, bad)
+        assert not bw._product_ok(a, b, c[:-1])
