@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mont", action="store_true", help="skip the Montgomery-butterfly (Algorithm 5) comparison")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in schedule instead of the autotuner's")
+    ap.add_argument("--clock-warm", type=float, default=0.5,
+                    help="seconds of untimed round trips before each policy's warm-up steps, so that the "
+                         "timed steps run at working clocks also when the schedule comes from the cache")
     ap.add_argument("--workload", default="batch64",
                     choices=["batch64", "single1k", "u64", "polymul", "serving", "bigmul", "table1", "pointwise"],
                     help="batch64 (default, the headline line); the others print their own JSON line")
@@ -256,6 +259,7 @@ def main():
         else:  # each butterfly gets its own best schedule (cached per GPU and shape)
             autotune.tune(ctx, x, p, w, policy=policy)
         schedules[policy] = ctx.get_plan(l, cfg.word_bits)
+        autotune.warm(ctx, x, p, w, policy, args.clock_warm)
         sec, kernels = time_steps(ctx, x, p, w, policy, args.steps, args.warmup)
         res[policy] = (sec, kernels)
     # the other policies once more under the lazy schedule: the butterflies alone compared

@@ -73,9 +73,9 @@ def _time(ctx, x, p, w, policy, reps):
     return ev0.elapsed_time(ev1) / reps
 
 
-def _warm(ctx, x, p, w, policy, seconds):
-    """Run the transform until the GPU has been busy for `seconds`: the first candidates
-    would otherwise be timed on a GPU that has not reached its working clocks."""
+def warm(ctx, x, p, w, policy, seconds):
+    """Run the transform until the GPU has been busy for `seconds`: whatever is timed first
+    would otherwise run on a GPU that has not reached its working clocks."""
     kw = {"plain": policy == "plain", "mont": policy == "mont"}
     t0 = time.time()
     while time.time() - t0 < seconds:
@@ -118,7 +118,7 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
     default = dict(ctx.get_plan(log2_len, word_bits))
     trials = []
     t0 = time.time()
-    _warm(ctx, x, p, omega, policy, 1.0)
+    warm(ctx, x, p, omega, policy, 1.0)
     for cand in candidates(ctx, log2_len, word_bits, batch):
         ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
         ms = _time(ctx, x, p, omega, policy, reps)
