@@ -77,8 +77,6 @@ bool prime_cached(hntt_ctx *ctx, uint64_t p) {
 
 int max_whole_log(int word_bits) { return word_bits == 32 ? 12 : 11; }
 
-int tpt_of(int n) { return n > 4 ? (1 << (n - 4)) : 1; }
-
 }  // namespace
 
 namespace hntt {

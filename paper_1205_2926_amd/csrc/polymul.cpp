@@ -250,7 +250,7 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
   if (rc) return rc;
   const std::vector<int> &logs = sz.logs;
   const std::vector<int> &class_count = sz.class_count;
-  const size_t ws_words = sz.ws_words, chunks_ws = sz.chunks_ws, chunks_out = sz.chunks_out;
+  const size_t chunks_ws = sz.chunks_ws, chunks_out = sz.chunks_out;
   rc = ensure_device(ctx);
   if (rc) return rc;
   int prev = -1;
