@@ -164,6 +164,29 @@ def test_mixed_batch_one_call(ctx, orc):
                                       orc.forward(x, l, p, _omega(orc, p, g, l)))
 
 
+@pytest.mark.parametrize("policy", POLICIES)
+@pytest.mark.parametrize("wb,l,batch", [(32, 12, 131), (32, 14, 70), (64, 13, 66)], ids=str)
+def test_batches_above_one_launch(ctx, orc, wb, l, batch, policy):
+    """Batches larger than one launch takes (64 transforms) run as several launches with a
+    ragged last one: every transform equal to its own single-transform call, and a spread of
+    them (first and last of each launch) against the oracle."""
+    p, g = (P30, G30) if wb == 32 else (P62, G62)
+    dt = _np_dtype(wb)
+    w = _omega(orc, p, g, l)
+    x = uniform_residues(500 + l, (batch, 1 << l), p, dt)
+    t = dev(x)
+    ctx.ntt_forward(t, p, w, **_kw(policy))
+    got = host(t, dt)
+    for b in sorted({0, 63, 64, 127, 128, batch - 1} & set(range(batch))):
+        np.testing.assert_array_equal(got[b].astype(np.uint64), orc.forward(x[b], l, p, w), err_msg=str(b))
+    for b in range(batch):
+        one = dev(x[b])
+        ctx.ntt_forward(one, p, w, **_kw(policy))
+        np.testing.assert_array_equal(host(one, dt), got[b], err_msg=str(b))
+    ctx.ntt_inverse(t, p, w, **_kw(policy))
+    np.testing.assert_array_equal(host(t, dt), x)
+
+
 @pytest.mark.parametrize("l", [5, 12, 20])
 def test_closed_forms_and_extremes(ctx, orc, l):
     p, g = P30, G30
