@@ -60,6 +60,13 @@ enum {
 #define HNTT_MONT 0x8u         /* Montgomery butterflies: Algorithm 5 (Section 4) forward and
                                   Algorithm 4 with Montgomery's product inverse; tables hold
                                   one word W beta mod p per root; same ranges and bounds as lazy */
+#define HNTT_VALIDATE 0x10u    /* check on the device that every input word is below p (the
+                                  [0,p) precondition of the transforms and of the pointwise
+                                  product) before anything else is enqueued: an input outside
+                                  it fails the call with EINVAL naming the first such
+                                  descriptor, and no data is changed.  The check waits for the
+                                  stream (a host synchronisation), so it cannot be used while
+                                  the stream is being captured into a graph. */
 
 typedef struct hntt_ctx hntt_ctx;
 
@@ -104,7 +111,7 @@ typedef struct {
  * Descriptors may mix primes, lengths and word sizes; descriptors that share
  * (p, omega, log2_len, word_bits) are transformed by the same launches.
  * Two descriptors must not name overlapping data.  flags: HNTT_PLAIN or
- * HNTT_MONT (not both: EINVAL), HNTT_NO_NORMALIZE.
+ * HNTT_MONT (not both: EINVAL), HNTT_NO_NORMALIZE, HNTT_VALIDATE.
  * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
 int hntt_ntt_forward(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream);
 
@@ -118,7 +125,8 @@ int hntt_ntt_inverse(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t f
  * (device pointers; c may alias a or b).  Needs p < 2^31 for 32-bit words and
  * p < 2^62 for 64-bit words; inputs in [0,p), output in [0,p).  Used between
  * forward and inverse transforms to multiply polynomials (the convolution
- * theorem behind the application named in Section 1).
+ * theorem behind the application named in Section 1).  flags: 0 or
+ * HNTT_VALIDATE (checks a and b).
  * Errors: EINVAL, EUNSUPPORTED, EDEVICE. */
 typedef struct {
   uint64_t p;
@@ -246,7 +254,8 @@ uint64_t hntt_find_prime(uint32_t bits, uint32_t v);
 int hntt_shoup_constant(uint64_t w, uint64_t p, uint32_t word_bits, uint64_t *wprime_out);
 
 /* Check descriptors as hntt_ntt_forward would, without touching the device.
- * Returns HNTT_OK or the error the transform call would return. */
+ * Returns HNTT_OK or the error the transform call would return (HNTT_VALIDATE
+ * is accepted; its device check of the data runs only in the transform calls). */
 int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags);
 
 /* ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 #include <tuple>
 #include <vector>
 
+#include "check_kernels.hpp"
 #include "hntt_internal.hpp"
 #include "ntt_kernels.hpp"
 #include "numtheory.hpp"
@@ -427,11 +428,45 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const Plan &plan, const std::v
   return HNTT_OK;
 }
 
+// HNTT_VALIDATE: one range check per array, all lowering one device word to the
+// smallest index with a word >= its bound, then a wait for the stream to read it.
+// `arrays` holds (data, words, word_bits, bound, index).
+struct CheckedArray {
+  const void *data;
+  uint64_t len;
+  int word_bits;
+  uint64_t bound;
+  uint32_t index;
+};
+
+int check_inputs(hntt_ctx *ctx, const std::vector<CheckedArray> &arrays, hipStream_t stream) {
+  if (!ctx->check_flag) {
+    hipError_t e = hipMalloc(&ctx->check_flag, 256);
+    if (e != hipSuccess) {
+      ctx->check_flag = nullptr;
+      return hip_status(ctx, e, "hipMalloc(check flag)");
+    }
+  }
+  const uint32_t none = 0xffffffffu;
+  hipError_t e = launch_set_flag(ctx->check_flag, none, stream);
+  for (size_t i = 0; e == hipSuccess && i < arrays.size(); ++i) {
+    const CheckedArray &a = arrays[i];
+    e = launch_range_check(a.word_bits, a.data, a.len, a.bound, a.index, ctx->check_flag, stream);
+  }
+  uint32_t first = none;
+  if (e == hipSuccess) e = hipMemcpyAsync(&first, ctx->check_flag, sizeof first, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_status(ctx, e, "input check");
+  if (first != none) return set_error(ctx, HNTT_EINVAL, "descriptor %u: an input word is not below p", first);
+  return HNTT_OK;
+}
+
 int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream, bool inverse) {
   if (!ctx) return HNTT_EINVAL;
   ctx->last_error.clear();
   if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
-  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE | HNTT_MONT)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE | HNTT_MONT | HNTT_VALIDATE))
+    return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
   if ((flags & HNTT_PLAIN) && (flags & HNTT_MONT))
     return set_error(ctx, HNTT_EINVAL, "HNTT_PLAIN and HNTT_MONT select different butterflies");
   // group descriptors that share parameters; validate everything before enqueueing anything
@@ -447,6 +482,13 @@ int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, v
   if (rc) return rc;
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return set_error(ctx, HNTT_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  if (flags & HNTT_VALIDATE) {
+    std::vector<CheckedArray> arrays;
+    for (size_t i = 0; i < n; ++i)
+      arrays.push_back({descs[i].data, (uint64_t)1 << descs[i].log2_len, (int)descs[i].word_bits, descs[i].p,
+                        (uint32_t)i});
+    if ((rc = check_inputs(ctx, arrays, (hipStream_t)stream))) return rc;
+  }
   for (auto &kv : groups) {
     const uint64_t p = std::get<0>(kv.first), omega = std::get<1>(kv.first);
     const int l = std::get<2>(kv.first), bits = std::get<3>(kv.first);
@@ -510,7 +552,8 @@ int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flag
   if (!ctx) return HNTT_EINVAL;
   ctx->last_error.clear();
   if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
-  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE | HNTT_MONT)) return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_NORMALIZE | HNTT_MONT | HNTT_VALIDATE))
+    return set_error(ctx, HNTT_EINVAL, "unknown flag bits");
   if ((flags & HNTT_PLAIN) && (flags & HNTT_MONT))
     return set_error(ctx, HNTT_EINVAL, "HNTT_PLAIN and HNTT_MONT select different butterflies");
   for (size_t i = 0; i < n; ++i) {
@@ -524,7 +567,7 @@ int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint3
   if (!ctx) return HNTT_EINVAL;
   ctx->last_error.clear();
   if (n && !descs) return set_error(ctx, HNTT_EINVAL, "descs is NULL");
-  if (flags) return set_error(ctx, HNTT_EINVAL, "pointwise_mul takes no flags");
+  if (flags & ~HNTT_VALIDATE) return set_error(ctx, HNTT_EINVAL, "pointwise_mul takes only HNTT_VALIDATE");
   for (size_t i = 0; i < n; ++i) {
     const hntt_pw_desc &d = descs[i];
     if (d.word_bits != 32 && d.word_bits != 64) return set_error(ctx, HNTT_EINVAL, "word_bits must be 32 or 64");
@@ -538,6 +581,16 @@ int hntt_pointwise_mul(hntt_ctx *ctx, const hntt_pw_desc *descs, size_t n, uint3
   int rc = ensure_device(ctx);
   if (rc) return rc;
   DeviceGuard guard(ctx->device);
+  if (!guard.ok) return set_error(ctx, HNTT_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  if (flags & HNTT_VALIDATE) {
+    std::vector<CheckedArray> arrays;
+    for (size_t i = 0; i < n; ++i) {
+      const hntt_pw_desc &d = descs[i];
+      arrays.push_back({d.a, d.len, (int)d.word_bits, d.p, (uint32_t)i});
+      arrays.push_back({d.b, d.len, (int)d.word_bits, d.p, (uint32_t)i});
+    }
+    if ((rc = check_inputs(ctx, arrays, (hipStream_t)stream))) return rc;
+  }
   for (size_t i = 0; i < n; ++i) {
     const hntt_pw_desc &d = descs[i];
     hipError_t e = launch_pointwise((int)d.word_bits, d.p, d.a, d.b, d.c, d.len, (hipStream_t)stream);

@@ -72,12 +72,15 @@ struct hntt_ctx {
   std::map<std::pair<int, int>, hntt_tuning> tuning;  // (log2_len, word_bits) -> schedule override
   std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
   hntt_polymul_plan *poly_cache = nullptr;  // last plan of hntt_polymul_crt
+  uint32_t *check_flag = nullptr;            // device word for HNTT_VALIDATE (allocated on first use)
   void release_poly_cache();
   bool trace = false;
   std::vector<hntt::TraceEvent> trace_pending;
   std::map<std::string, hntt::TraceAcc> trace_acc;
   void release_device_state() {
     tables.clear();
+    if (check_flag) (void)hipFree(check_flag);
+    check_flag = nullptr;
     for (auto &ev : trace_pending) {
       (void)hipEventDestroy(ev.start);
       (void)hipEventDestroy(ev.stop);

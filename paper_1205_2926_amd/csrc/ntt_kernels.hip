@@ -18,6 +18,7 @@
 //           length-C transform with root omega^R.
 // Forward: kCols then kRows (natural in, bit-reversed out).  Inverse: kRows
 // then kCols, with the split factor conj(omega)^(col*s) * L^-1 applied on load.
+#include "check_kernels.hpp"
 #include "modarith.hpp"
 #include "ntt_kernels.hpp"
 
@@ -73,6 +74,20 @@ __global__ void k_pointwise(uint64_t p64, uint64_t j64, uint64_t r2_64, const ty
   }
 }
 
+__global__ void k_set_flag(uint32_t *flag, uint32_t value) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = value;
+}
+
+// Lanes that saw an out-of-range word lower the flag with a vector atomic; the
+// rest only read.
+template <class T>
+__global__ void k_range_check(const T *__restrict__ x, uint64_t len, T bound, uint32_t index, uint32_t *first_bad) {
+  bool bad = false;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x)
+    bad |= x[i] >= bound;
+  if (bad) atomicMin(first_bad, index);
+}
+
 template <class T>
 T inv_mod_pow2(T p) {  // p^-1 mod 2^bits for odd p, by Newton iteration
   T x = p;             // correct to 3 bits
@@ -112,6 +127,26 @@ hipError_t launch_debug_butterfly(int kind, int word_bits, uint64_t p, const voi
     hipLaunchKernelGGL(k_debug_butterfly<Word64>, dim3(blocks), dim3(threads), 0, stream, kind, p,
                        (const T *)x, (const T *)y, (const T *)w, (const T *)wp, (T *)xo, (T *)yo, n);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_flag(uint32_t *flag, uint32_t value, hipStream_t stream) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, stream, flag, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_range_check(int word_bits, const void *x, uint64_t len, uint64_t bound, uint32_t index,
+                              uint32_t *first_bad, hipStream_t stream) {
+  if (len == 0) return hipSuccess;
+  const int threads = 256;
+  const uint64_t want = (len + threads - 1) / threads;
+  const int blocks = (int)(want < 4096 ? want : 4096);
+  if (word_bits == 32)
+    hipLaunchKernelGGL(k_range_check<uint32_t>, dim3(blocks), dim3(threads), 0, stream, (const uint32_t *)x, len,
+                       (uint32_t)bound, index, first_bad);
+  else
+    hipLaunchKernelGGL(k_range_check<uint64_t>, dim3(blocks), dim3(threads), 0, stream, (const uint64_t *)x, len,
+                       bound, index, first_bad);
   return hipGetLastError();
 }
 

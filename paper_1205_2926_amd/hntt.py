@@ -25,6 +25,7 @@ PLAIN = 0x1
 NO_NORMALIZE = 0x2
 NO_GRAPH = 0x4
 MONT = 0x8
+VALIDATE = 0x10
 POLICY_FLAGS = {"lazy": 0, "plain": PLAIN, "mont": MONT}
 
 _c_u64 = ctypes.c_uint64
@@ -280,22 +281,24 @@ class Context:
 
     # -- transforms --------------------------------------------------------------------------------
     def ntt_forward(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None,
-                    mont: bool = False):
+                    mont: bool = False, validate: bool = False):
         """In-place forward NTT of every row of x (natural in, bit-reversed out).  plain selects
-        Algorithm 2, mont Algorithm 5; the default is Algorithm 3."""
-        self._transform(self.lib.hntt_ntt_forward, x, p, omega, plain, normalize, stream, mont)
+        Algorithm 2, mont Algorithm 5; the default is Algorithm 3.  validate checks on the
+        device that every input word is below p first (HNTT_VALIDATE)."""
+        self._transform(self.lib.hntt_ntt_forward, x, p, omega, plain, normalize, stream, mont, validate)
         return x
 
     def ntt_inverse(self, x, p: int, omega: int, plain: bool = False, normalize: bool = True, stream=None,
-                    mont: bool = False):
+                    mont: bool = False, validate: bool = False):
         """In-place inverse NTT of every row of x (bit-reversed in, natural out, times L^-1)."""
-        self._transform(self.lib.hntt_ntt_inverse, x, p, omega, plain, normalize, stream, mont)
+        self._transform(self.lib.hntt_ntt_inverse, x, p, omega, plain, normalize, stream, mont, validate)
         return x
 
-    def _transform(self, fn, x, p, omega, plain, normalize, stream, mont=False):
+    def _transform(self, fn, x, p, omega, plain, normalize, stream, mont=False, validate=False):
         rows = self.rows_of(x) if isinstance(x, torch.Tensor) else list(x)
         arr = self.descs(rows, p, omega)
-        flags = (PLAIN if plain else 0) | (MONT if mont else 0) | (0 if normalize else NO_NORMALIZE)
+        flags = ((PLAIN if plain else 0) | (MONT if mont else 0) | (0 if normalize else NO_NORMALIZE) |
+                 (VALIDATE if validate else 0))
         dev = rows[0].device if rows else torch.device("cuda", self.device)
         self._check(fn(self.handle, arr, len(rows), flags, _stream_handle(stream, dev)))
 
@@ -307,10 +310,12 @@ class Context:
     def validate(self, arr, flags: int = 0) -> int:
         return int(self.lib.hntt_validate(self.handle, arr, len(arr), flags))
 
-    def pointwise_mul(self, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, p: int, stream=None):
+    def pointwise_mul(self, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, p: int, stream=None,
+                      validate: bool = False):
         wb = _word_bits(a)
         d = (PwDesc * 1)(PwDesc(p, a.data_ptr(), b.data_ptr(), c.data_ptr(), a.numel(), wb, 0))
-        self._check(self.lib.hntt_pointwise_mul(self.handle, d, 1, 0, _stream_handle(stream, a.device)))
+        self._check(self.lib.hntt_pointwise_mul(self.handle, d, 1, VALIDATE if validate else 0,
+                                                _stream_handle(stream, a.device)))
         return c
 
     @staticmethod

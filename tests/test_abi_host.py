@@ -132,7 +132,20 @@ def test_montgomery_flag_checks(ctx):
     assert "HNTT_MONT" in ctx.last_error()
     p = 2013265921  # < beta/2 but not < beta/4
     assert ctx.validate(_desc(p=p, omega=pow(31, (p - 1) >> 10, p)), hntt.MONT) == hntt.EUNSUPPORTED
-    assert ctx.validate(arr, 0x10) == hntt.EINVAL
+    assert ctx.validate(arr, 0x20) == hntt.EINVAL
+    assert ctx.validate(arr, hntt.VALIDATE) == hntt.OK  # host checks only; the device check is per call
+
+
+def test_validate_flag_value_matches_header():
+    import re
+    text = open(os.path.join(ROOT, "include", "hntt.h")).read()
+    assert int(re.search(r"#define HNTT_VALIDATE (0x[0-9a-f]+)u", text).group(1), 16) == hntt.VALIDATE
+
+
+def test_pointwise_flags_checked_on_host(ctx):
+    d = (hntt.PwDesc * 1)(hntt.PwDesc(P30, 4096, 4096, 4096, 16, 32, 0))
+    assert ctx.lib.hntt_pointwise_mul(ctx.handle, d, 1, hntt.PLAIN, None) == hntt.EINVAL
+    assert "HNTT_VALIDATE" in ctx.last_error()
 
 
 def test_composite_modulus_rejected(ctx):

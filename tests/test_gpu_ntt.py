@@ -187,6 +187,43 @@ def test_batches_above_one_launch(ctx, orc, wb, l, batch, policy):
     np.testing.assert_array_equal(host(t, dt), x)
 
 
+@pytest.mark.parametrize("wb,l", [(32, 10), (32, 16), (64, 13)], ids=str)
+def test_validate_flag(ctx, orc, wb, l):
+    """HNTT_VALIDATE: in-range batches transform as without it; a batch with a word at or above
+    p fails with EINVAL naming the first such descriptor, and no array is changed."""
+    p, g = (P30, G30) if wb == 32 else (P62, G62)
+    dt = _np_dtype(wb)
+    w = _omega(orc, p, g, l)
+    x = uniform_residues(600 + l, (3, 1 << l), p, dt)
+    for inverse in (False, True):
+        fn = ctx.ntt_inverse if inverse else ctx.ntt_forward
+        a, b = dev(x), dev(x)
+        fn(a, p, w)
+        fn(b, p, w, validate=True)
+        np.testing.assert_array_equal(host(b, dt), host(a, dt))
+        for bad_rows, bad_value, first in (([1, 2], p, 1), ([2], (1 << wb) - 1, 2), ([0], p + 5, 0)):
+            y = x.copy()
+            for r in bad_rows:
+                y[r, (r * 7919) % (1 << l)] = dt(bad_value)
+            t = dev(y)
+            with pytest.raises(hntt.HnttError) as err:
+                fn(t, p, w, validate=True)
+            assert err.value.status == hntt.EINVAL and f"descriptor {first}" in str(err.value)
+            np.testing.assert_array_equal(host(t, dt), y)
+    # the pointwise product checks both operands
+    a, b = dev(x[0]), dev(x[1])
+    c = dev(x[2])
+    ctx.pointwise_mul(a, b, c, p, validate=True)
+    np.testing.assert_array_equal(host(c, dt).astype(np.uint64), orc.pointwise(x[0], x[1], p))
+    yb = x[1].copy()
+    yb[-1] = dt(p)
+    c = dev(x[2])
+    with pytest.raises(hntt.HnttError) as err:
+        ctx.pointwise_mul(a, dev(yb), c, p, validate=True)
+    assert err.value.status == hntt.EINVAL
+    np.testing.assert_array_equal(host(c, dt), x[2])
+
+
 @pytest.mark.parametrize("l", [5, 12, 20])
 def test_closed_forms_and_extremes(ctx, orc, l):
     p, g = P30, G30
