@@ -85,7 +85,7 @@ def pin_forward_naive(orc, max_l=7):
             assert got == to_bitrev(naive_dft(a, p, w)), (p, l)
 
 
-def pin_forward_sympy(orc, ls=(8, 10)):
+def pin_forward_sympy(orc, ls=(8, 10, 11, 12)):
     from sympy.discrete.transforms import ntt
     r = random.Random(12)
     for p, g in PRIMES[:3]:
@@ -108,7 +108,7 @@ def pin_inverse_naive(orc, max_l=7):
             assert got == a, (p, l)
 
 
-def pin_inverse_sympy(orc, ls=(9,)):
+def pin_inverse_sympy(orc, ls=(9, 12)):
     from sympy.discrete.transforms import intt
     r = random.Random(14)
     for p, g in PRIMES[:3]:
