@@ -177,6 +177,7 @@ __device__ __forceinline__ void bfly_w1(T &x, T &y, const Mod &m) {
 template <int Pol>
 __device__ __forceinline__ T mul_const(T x, const TwT<Pol> &tw, const Mod &m) {
   if constexpr (Pol == kPolicyMont) return mont_lazy<Wd>(x, tw, m.p, m.j);
+  else if constexpr (!kInverse) return shoup_lazy_mad<Wd>(x, tw.x, tw.y, m.p);
   else return shoup_lazy<Wd>(x, tw.x, tw.y, m.p);
 }
 
