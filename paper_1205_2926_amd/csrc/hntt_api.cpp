@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -240,14 +241,31 @@ static void heap_table(uint64_t root, int n, const TableForm &form, std::vector<
     for (size_t k = 0; k < ((size_t)1 << b); ++k) form.put(out, ((size_t)1 << b) + k, pw[k << (n - 1 - b)]);
 }
 
-int upload(hntt_ctx *ctx, const std::vector<uint64_t> &src, int bits, const void **out) {
+// Device copies of one table set, held locally until every upload has succeeded:
+// a failure part-way frees what was uploaded and leaves the context's buffers and
+// byte count as they were.
+struct PendingUploads {
+  std::vector<std::unique_ptr<DeviceBuffer>> bufs;
+  size_t bytes = 0;
+  void commit(hntt_ctx *ctx) {
+    for (auto &b : bufs) ctx->buffers.push_back(std::move(b));
+    bufs.clear();
+    ctx->bytes_held += bytes;
+    bytes = 0;
+  }
+};
+
+int upload(hntt_ctx *ctx, PendingUploads &pend, const std::vector<uint64_t> &src, int bits, const void **out) {
   const size_t bytes = src.size() * (bits / 8);
-  if (ctx->budget && ctx->bytes_held + bytes > ctx->budget)
+  if (ctx->budget && ctx->bytes_held + pend.bytes + bytes > ctx->budget)
     return set_error(ctx, HNTT_ENOMEM, "memory budget of %zu bytes exceeded", ctx->budget);
   auto buf = std::make_unique<DeviceBuffer>();
   if (bytes) {
     hipError_t e = hipMalloc(&buf->ptr, bytes);
-    if (e != hipSuccess) return hip_status(ctx, e, "hipMalloc(twiddle table)");
+    if (e != hipSuccess) {
+      buf->ptr = nullptr;
+      return hip_status(ctx, e, "hipMalloc(twiddle table)");
+    }
     buf->bytes = bytes;
     if (bits == 32) {
       std::vector<uint32_t> narrow(src.begin(), src.end());
@@ -257,10 +275,15 @@ int upload(hntt_ctx *ctx, const std::vector<uint64_t> &src, int bits, const void
     }
     if (e != hipSuccess) return hip_status(ctx, e, "hipMemcpy(twiddle table)");
   }
-  ctx->bytes_held += bytes;
+  pend.bytes += bytes;
   *out = buf->ptr;
-  ctx->buffers.push_back(std::move(buf));
+  pend.bufs.push_back(std::move(buf));
   return HNTT_OK;
+}
+
+const Tables *find_tables(const hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont) {
+  auto it = ctx->tables.find(std::make_tuple(p, omega, l, bits, mont));
+  return it == ctx->tables.end() ? nullptr : &it->second;
 }
 
 // Twiddle tables for one (p, omega, l, word_bits, form): built on the host once and kept on the device.
@@ -282,10 +305,11 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool 
   t.linv_p = mont ? 0 : shoup_constant(linv, p, bits);
   t.jinv = inv_mod_beta(p, bits);
   std::vector<uint64_t> tab;
+  PendingUploads pend;
   int rc;
   auto table = [&](uint64_t root, int n, const void **dst) -> int {
     heap_table(root, n, form, tab);
-    return upload(ctx, tab, bits, dst);
+    return upload(ctx, pend, tab, bits, dst);
   };
   if (!t.plan.split) {
     if ((rc = table(omega, l, &t.fwd))) return rc;
@@ -327,9 +351,10 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool 
       for (uint64_t hi = 0; hi < (1ull << (r - si)); ++hi)
         put(iv, ((1ull << si) + hi) * C + col, mulmod(linv, powmod(wc, bitrev((unsigned)hi, r - si), p), p));
     }
-    if ((rc = upload(ctx, f, bits, &t.tt_fwd))) return rc;
-    if ((rc = upload(ctx, iv, bits, &t.tt_inv))) return rc;
+    if ((rc = upload(ctx, pend, f, bits, &t.tt_fwd))) return rc;
+    if ((rc = upload(ctx, pend, iv, bits, &t.tt_inv))) return rc;
   }
+  pend.commit(ctx);
   auto ins = ctx->tables.emplace(key, t);
   *out = &ins.first->second;
   return HNTT_OK;
@@ -353,10 +378,11 @@ std::string pass_name(const PassParams &pp) {
   return buf;
 }
 
-// Launch one pass; with tracing on, bracket it with HIP events on the launch stream.
-hipError_t launch_traced(hntt_ctx *ctx, const PassParams &pp, const BatchPtrs &bp, hipStream_t stream) {
-  if (!ctx->trace) return launch_pass(pp, bp, stream);
-  TraceEvent ev{pass_name(pp), nullptr, nullptr};
+// Run one launch; with tracing on, bracket it with HIP events on the launch stream.
+hipError_t trace_launch(hntt_ctx *ctx, const std::string &name, hipStream_t stream,
+                        const std::function<hipError_t()> &launch) {
+  if (!ctx->trace) return launch();
+  TraceEvent ev{name, nullptr, nullptr};
   hipError_t e = hipEventCreate(&ev.start);
   if (e != hipSuccess) return e;
   if ((e = hipEventCreate(&ev.stop)) != hipSuccess) {
@@ -364,10 +390,14 @@ hipError_t launch_traced(hntt_ctx *ctx, const PassParams &pp, const BatchPtrs &b
     return e;
   }
   (void)hipEventRecord(ev.start, stream);
-  e = launch_pass(pp, bp, stream);
+  e = launch();
   (void)hipEventRecord(ev.stop, stream);
   ctx->trace_pending.push_back(ev);
   return e;
+}
+
+hipError_t launch_traced(hntt_ctx *ctx, const PassParams &pp, const BatchPtrs &bp, hipStream_t stream) {
+  return trace_launch(ctx, pass_name(pp), stream, [&]() { return launch_pass(pp, bp, stream); });
 }
 
 // Run every pass of one transform direction over a batch sharing (p, omega, l, word_bits).

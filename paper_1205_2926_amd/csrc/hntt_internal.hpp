@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -96,9 +97,14 @@ Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits);
 int check_tuning(const hntt_tuning &t, std::string *why);
 int ensure_device(hntt_ctx *ctx);
 int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, const Tables **out);
-// Launch wrapper that records HIP events around the launch when tracing is on.
+// The resident tables of (p, omega, l, bits, form), or null; builds nothing.
+const Tables *find_tables(const hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont);
+// Launch wrappers that record HIP events around the launch when tracing is on
+// (hntt_trace_*): any launch under a kernel name, or one NTT pass under its name.
 struct PassParams;
-hipError_t traced(hntt_ctx *ctx, const std::string &name, hipStream_t stream, hipError_t (*fn)(const void *, hipStream_t),
-                  const void *arg);
+struct BatchPtrs;
+hipError_t trace_launch(hntt_ctx *ctx, const std::string &name, hipStream_t stream,
+                        const std::function<hipError_t()> &launch);
+hipError_t launch_traced(hntt_ctx *ctx, const PassParams &pp, const BatchPtrs &bp, hipStream_t stream);
 int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, void *stream, bool inverse);
 }  // namespace hntt

@@ -184,7 +184,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
     pp.pm_off = pm_off;
     pp.zero_upper = !inverse;  // padded operands: the upper half is zero
     slots_for(pp, 0);
-    if ((e = launch_pass(pp, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly whole)");
+    if ((e = launch_traced(ctx, pp, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly whole)");
     return HNTT_OK;
   }
   PassParams cols = base, rows = base;
@@ -203,20 +203,22 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
   rows.pm_off = pm_off;
   cols.zero_upper = !inverse;  // padded operands: rows in the upper half are zero
   if (!inverse) {
-    if ((e = launch_pass(cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
-    if ((e = launch_pass(rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
+    if ((e = launch_traced(ctx, cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
+    if ((e = launch_traced(ctx, rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
   } else {
-    if ((e = launch_pass(rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
-    if ((e = launch_pass(cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
+    if ((e = launch_traced(ctx, rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
+    if ((e = launch_traced(ctx, cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
   }
   return HNTT_OK;
 }
 
 static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s) {
   hntt_ctx *ctx = pl->ctx;
+  const PolyArgs &a = pl->args;
   hipError_t e;
   int rc;
-  if ((e = launch_poly_prep(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly prep)");
+  if ((e = trace_launch(ctx, "poly_prep", s, [&]() { return launch_poly_prep(a, s); })) != hipSuccess)
+    return hip_err(ctx, e, "launch(poly prep)");
   for (const ClassWork &cw : pl->classes)
     if ((rc = run_class(ctx, cw, 0, pl->flags, s))) return rc;
   for (const ClassWork &cw : pl->classes)  // B_k transforms; their last pass multiplies into A_k
@@ -224,9 +226,11 @@ static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s) {
   for (const ClassWork &cw : pl->classes)
     if ((rc = run_class(ctx, cw, 2, pl->flags, s))) return rc;
   if (pl->big) {
-    if ((e = launch_big_crt(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(big crt)");
-    if ((e = launch_big_carry(pl->args, s)) != hipSuccess) return hip_err(ctx, e, "launch(big carry)");
-  } else if ((e = launch_poly_crt(pl->args, s)) != hipSuccess) {
+    if ((e = trace_launch(ctx, "big_crt", s, [&]() { return launch_big_crt(a, s); })) != hipSuccess)
+      return hip_err(ctx, e, "launch(big crt)");
+    if ((e = trace_launch(ctx, "big_carry", s, [&]() { return launch_big_carry(a, s); })) != hipSuccess)
+      return hip_err(ctx, e, "launch(big carry)");
+  } else if ((e = trace_launch(ctx, "poly_crt", s, [&]() { return launch_poly_crt(a, s); })) != hipSuccess) {
     return hip_err(ctx, e, "launch(poly crt)");
   }
   return HNTT_OK;

@@ -390,3 +390,36 @@ def test_schedule_independence(ctx, orc, wb, l, policy):
         ctx.ntt_inverse(t, p, w, **_kw(policy))
         np.testing.assert_array_equal(host(t, dt), x, err_msg=str(cand))
     ctx.set_tuning(l, wb)
+
+
+def test_memory_budget_exhausted_then_usable(orc):
+    """A context whose budget cannot hold a transform's tables refuses it with ENOMEM,
+    releases what it had uploaded for it, and keeps working.  Table sizes (u32 pairs):
+    2^10 whole 16 KiB; 2^16 split 8 KiB of per-stage tables + 64 KiB + 64 KiB of split
+    twiddles; 2^12 whole 64 KiB.  With a 100 KiB budget the 2^16 tables fail on their
+    last upload; the 2^12 tables fit only if that failure left nothing counted."""
+    print("memory budget", flush=True)
+    c = hntt.Context(0, mem_budget=100 * 1024)
+    try:
+        p = P30
+
+        def run(l, seed):
+            w = hntt.root_of_unity(p, l)
+            x = uniform_residues(seed, (1, 1 << l), p, np.uint32)
+            t = dev(x)
+            c.ntt_forward(t, p, w)
+            np.testing.assert_array_equal(host(t, np.uint32)[0], orc.forward(x[0], l, p, w).astype(np.uint32))
+
+        run(10, 60)
+        w16 = hntt.root_of_unity(p, 16)
+        x16 = uniform_residues(61, (1, 1 << 16), p, np.uint32)
+        t16 = dev(x16)
+        for _ in range(2):  # a retry fails the same way: nothing was counted twice
+            with pytest.raises(hntt.HnttError) as ei:
+                c.ntt_forward(t16, p, w16)
+            assert ei.value.status == hntt.ENOMEM and "budget" in c.last_error()
+        np.testing.assert_array_equal(host(t16, np.uint32), x16)  # nothing was enqueued
+        run(12, 62)
+        run(10, 63)
+    finally:
+        c.close()
