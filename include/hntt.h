@@ -201,6 +201,33 @@ int hntt_polymul_workspace_size(const hntt_poly_desc *descs, size_t n, size_t *b
 int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *plan, void *stream);
 void hntt_polymul_plan_destroy(hntt_polymul_plan *plan);
 
+/* Allocation-free form of hntt_polymul_crt, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).  Same
+ * products, descriptors and results as hntt_polymul_crt; the difference is
+ * where the workspace lives and what the call may do:
+ *   - the workspace (reduced, padded operands of the three primes and the
+ *     batch's metadata) is a static device array of HNTT_STATIC_SCRATCH_BYTES
+ *     that the library holds on every GPU it is loaded on until the process
+ *     ends; a batch needing more (hntt_polymul_workspace_size) fails with
+ *     ENOMEM before anything is enqueued;
+ *   - the call issues no hipMalloc/hipFree and builds no twiddle table: the
+ *     tables of every padded length in the batch must already be resident on
+ *     ctx (made by an earlier hntt_polymul_crt or hntt_polymul_plan_create with
+ *     products of the same padded lengths and flags); otherwise EUNSUPPORTED,
+ *     nothing enqueued;
+ *   - kernels are enqueued directly (no graph); the metadata goes to the device
+ *     with one asynchronous host-to-device copy on `stream`;
+ *   - every call on one GPU shares that GPU's workspace and leaves its contents
+ *     there; nothing in it needs to start at zero.  Calls in stream order on one
+ *     stream are safe; calls that overlap on one GPU (other streams, other
+ *     contexts, other host threads) race on the workspace and give wrong
+ *     results.
+ * flags: HNTT_PLAIN, HNTT_NO_GRAPH (accepted, implied).
+ * Errors: EINVAL, EUNSUPPORTED (padded length above 2^23, or tables not yet
+ * resident), ENOMEM (batch larger than the static workspace), EDEVICE. */
+#define HNTT_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+int hntt_polymul_crt_static(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Large-integer multiplication (the application that Section 1 names for fast
  * transforms): out = a * b for non-negative integers given as little-endian

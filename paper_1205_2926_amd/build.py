@@ -27,7 +27,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
-SOURCES = ["ntt_kernels.hip", "hntt_api.cpp", "polymul.cpp", "polymul.hip",
+SOURCES = ["ntt_kernels.hip", "hntt_api.cpp", "polymul.cpp", "polymul.hip", "static_scratch.hip",
            ("ntt_pass.hip", "u32_fwd", ["-DHNTT_WORD=32", "-DHNTT_INVERSE=0"]),
            ("ntt_pass.hip", "u32_inv", ["-DHNTT_WORD=32", "-DHNTT_INVERSE=1"]),
            ("ntt_pass.hip", "u64_fwd", ["-DHNTT_WORD=64", "-DHNTT_INVERSE=0"]),

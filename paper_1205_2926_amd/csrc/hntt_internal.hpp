@@ -73,6 +73,7 @@ struct hntt_ctx {
   std::map<std::pair<int, int>, hntt_tuning> tuning;  // (log2_len, word_bits) -> schedule override
   std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
   hntt_polymul_plan *poly_cache = nullptr;  // last plan of hntt_polymul_crt
+  std::vector<unsigned char> static_meta;    // host image of the last hntt_polymul_crt_static metadata
   uint32_t *check_flag = nullptr;            // device word for HNTT_VALIDATE (allocated on first use)
   void release_poly_cache();
   bool trace = false;

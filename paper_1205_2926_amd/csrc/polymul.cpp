@@ -16,6 +16,7 @@
 #include "ntt_kernels.hpp"
 #include "numtheory.hpp"
 #include "polymul_kernels.hpp"
+#include "static_scratch.hpp"
 
 using namespace hntt;
 
@@ -240,8 +241,11 @@ static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s) {
 
 // Plan a batch of products: coefficient vectors (big = false) or large-integer
 // limb products (big = true); descriptors are checked on the host first.
+// no_alloc: the workspace is the static device array (given as `workspace`), the
+// twiddle tables must already be resident, and nothing is allocated on the device.
 static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, bool big,
-                       void *workspace, size_t workspace_bytes, void *stream, hntt_polymul_plan **out) {
+                       void *workspace, size_t workspace_bytes, void *stream, hntt_polymul_plan **out,
+                       bool no_alloc = false) {
   if (!ctx || !out) return HNTT_EINVAL;
   ctx->last_error.clear();
   *out = nullptr;
@@ -283,7 +287,13 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
     for (int k = 0; k < 3; ++k) {
       const uint64_t q = kPrimes[k];
       const uint64_t omega = powmod(primitive_root(q), (q - 1) >> l, q);
-      if ((rc = get_tables(ctx, q, omega, l, 32, false, &cw.tab[k]))) return rc;
+      if (!no_alloc) {
+        if ((rc = get_tables(ctx, q, omega, l, 32, false, &cw.tab[k]))) return rc;
+      } else if (!(cw.tab[k] = find_tables(ctx, q, omega, l, 32, false))) {
+        return perr(ctx, HNTT_EUNSUPPORTED,
+                    "twiddle tables of padded length 2^%d are not resident on this context (an earlier "
+                    "hntt_polymul_crt or plan with products of that length builds them)", l);
+      }
     }
     classes.push_back(cw);
   }
@@ -291,6 +301,7 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
   // arena: workspace, then the metadata tables
   const size_t off_pairs = sz.off_pairs, off_cws = sz.off_cws, off_cout = sz.off_cout, off_xf = sz.off_xf;
   const size_t total = sz.total;
+  if (no_alloc && !workspace) return perr(ctx, HNTT_EINVAL, "no workspace");
   if (workspace) {
     if (workspace_bytes < total)
       return perr(ctx, HNTT_ENOMEM, "workspace of %zu bytes is smaller than the %zu this plan needs", workspace_bytes,
@@ -384,6 +395,9 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
     hntt_polymul_plan_destroy(pl.release());
     return r;
   }
+  // The static form's plan lives for one call: its host image stays with the
+  // context until the next such call.
+  if (no_alloc) ctx->static_meta.swap(meta);
   *out = pl.release();
   return HNTT_OK;
 }
@@ -512,6 +526,40 @@ int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint3
   if (n == 0) return HNTT_OK;
   if (!descs) return perr(ctx, HNTT_EINVAL, "descs is NULL");
   return one_shot(ctx, descs, n, flags, false, stream);
+}
+
+int hntt_polymul_crt_static(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *stream) {
+  if (!ctx) return HNTT_EINVAL;
+  ctx->last_error.clear();
+  if (n == 0) return HNTT_OK;
+  if (!descs) return perr(ctx, HNTT_EINVAL, "descs is NULL");
+  if (flags & ~(HNTT_PLAIN | HNTT_NO_GRAPH)) return perr(ctx, HNTT_EINVAL, "unknown flag bits");
+  // the size is known from the lengths: an oversized batch fails before the device is touched
+  Sizing sz;
+  int rc = size_batch(ctx, descs, n, true, &sz);
+  if (rc) return rc;
+  if (sz.total > kStaticScratchBytes)
+    return perr(ctx, HNTT_ENOMEM, "batch needs %zu bytes of workspace; the static workspace holds %zu", sz.total,
+                kStaticScratchBytes);
+  if ((rc = ensure_device(ctx))) return rc;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(ctx->device) != hipSuccess) return perr(ctx, HNTT_EDEVICE, "hipSetDevice failed");
+  struct Restore {
+    int d;
+    ~Restore() {
+      if (d >= 0) (void)hipSetDevice(d);
+    }
+  } restore{prev};
+  void *ws = nullptr;
+  hipError_t e = static_scratch_address(ctx->device, &ws);
+  if (e != hipSuccess) return hip_err(ctx, e, "address of the static workspace");
+  hntt_polymul_plan *pl = nullptr;
+  rc = plan_create(ctx, descs, n, flags | HNTT_NO_GRAPH, false, ws, kStaticScratchBytes, stream, &pl, true);
+  if (rc) return rc;
+  rc = enqueue_plan(pl, (hipStream_t)stream);
+  hntt_polymul_plan_destroy(pl);  // host bookkeeping only: the workspace is not the plan's
+  return rc;
 }
 
 int hntt_bigmul(hntt_ctx *ctx, const hntt_bigmul_desc *descs, size_t n, uint32_t flags, void *stream) {

@@ -26,6 +26,7 @@ NO_NORMALIZE = 0x2
 NO_GRAPH = 0x4
 MONT = 0x8
 VALIDATE = 0x10
+STATIC_SCRATCH_BYTES = 32 << 20  # HNTT_STATIC_SCRATCH_BYTES
 POLICY_FLAGS = {"lazy": 0, "plain": PLAIN, "mont": MONT}
 
 _c_u64 = ctypes.c_uint64
@@ -75,6 +76,7 @@ SIGNATURES = {
     "hntt_ntt_inverse": (ctypes.c_int, [_c_vp, ctypes.POINTER(Desc), ctypes.c_size_t, _c_u32, _c_vp]),
     "hntt_pointwise_mul": (ctypes.c_int, [_c_vp, ctypes.POINTER(PwDesc), ctypes.c_size_t, _c_u32, _c_vp]),
     "hntt_polymul_crt": (ctypes.c_int, [_c_vp, ctypes.POINTER(PolyDesc), ctypes.c_size_t, _c_u32, _c_vp]),
+    "hntt_polymul_crt_static": (ctypes.c_int, [_c_vp, ctypes.POINTER(PolyDesc), ctypes.c_size_t, _c_u32, _c_vp]),
     "hntt_polymul_plan_create": (ctypes.c_int, [_c_vp, ctypes.POINTER(PolyDesc), ctypes.c_size_t, _c_u32, _c_vp,
                                                 ctypes.c_size_t, _c_vp, ctypes.POINTER(_c_vp)]),
     "hntt_polymul_plan_workspace_bytes": (ctypes.c_size_t, [_c_vp]),
@@ -336,6 +338,17 @@ class Context:
         dev = outs[0].device if outs else torch.device("cuda", self.device)
         flags = (PLAIN if plain else 0) | (0 if graph else NO_GRAPH)
         self._check(self.lib.hntt_polymul_crt(self.handle, arr, len(pairs), flags, _stream_handle(stream, dev)))
+        return outs
+
+    def polymul_crt_static(self, pairs: Sequence[tuple[torch.Tensor, torch.Tensor]], outs: Sequence[torch.Tensor],
+                           plain: bool = False, stream=None):
+        """hntt_polymul_crt_static: the same products in the library's static device workspace
+        (no device allocation; the twiddle tables of every length must already be resident)."""
+        arr = self.poly_descs(pairs, outs)
+        dev = outs[0].device if outs else torch.device("cuda", self.device)
+        flags = PLAIN if plain else 0
+        self._check(self.lib.hntt_polymul_crt_static(self.handle, arr, len(pairs), flags,
+                                                     _stream_handle(stream, dev)))
         return outs
 
     def polymul_plan(self, pairs, outs, plain: bool = False, graph: bool = True, workspace: torch.Tensor = None,
