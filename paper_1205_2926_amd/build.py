@@ -47,6 +47,23 @@ def _compile(spec) -> str:
     return obj
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "valu_rates.hip")
+PROBE_BIN = os.path.join(HERE, "probe", "valu_rates")
+
+
+def build_probe() -> str:
+    """The instruction-rate, shader-clock and copy-bandwidth probe (a standalone program)."""
+    tmp = PROBE_BIN + ".tmp"
+    cmd = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on the rate probe")
+    os.replace(tmp, PROBE_BIN)
+    return PROBE_BIN
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     sources = list(SOURCES)
@@ -59,6 +76,7 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link of libhntt.so failed")
     os.replace(tmp, LIB)
+    build_probe()
     if verbose:
         print(f"built {LIB}")
     return LIB

@@ -55,29 +55,38 @@ void t1_plan_destroy(t1_plan *pl) {
   free(pl);
 }
 
-/* Algorithm 2: X, Y in [0,p) -> X + Y mod p, W (X - Y) mod p, both in [0,p). */
-static inline void bfly2(uint64_t *x, uint64_t *y, uint64_t w, uint64_t wp, uint64_t p) {
-  const uint64_t X = *x, Y = *y;
-  uint64_t s = X + Y;
-  if (s >= p) s -= p;
-  uint64_t t = X - Y;
-  if ((int64_t)t < 0) t += p;
-  const uint64_t q = (uint64_t)(((u128)wp * t) >> 64);
-  uint64_t r = w * t - q * p;
-  if (r >= p) r -= p;
-  *x = s;
-  *y = r;
+/* Word arithmetic shared by both butterflies.  x >= m ? x - m : x without a
+ * branch (x - m wraps above x exactly when x < m). */
+static inline uint64_t csub64(uint64_t x, uint64_t m) {
+  const uint64_t d = x - m;
+  return d < x ? d : x;
 }
 
-/* Algorithm 3: X, Y in [0,2p) -> X + Y and W (X - Y), both in [0,2p) (p < 2^62). */
-static inline void bfly3(uint64_t *x, uint64_t *y, uint64_t w, uint64_t wp, uint64_t p2) {
-  const uint64_t X = *x, Y = *y;
-  uint64_t s = X + Y;
-  if (s >= p2) s -= p2;
-  const uint64_t t = X - Y + p2;
+/* Shoup's product: for any t < 2^64 and W' = floor(W 2^64 / p), the quotient
+ * estimate Q = hi(W' t) leaves W t - Q p in [0, 2p); only the low words of the two
+ * products are needed. */
+static inline uint64_t shoup64(uint64_t t, uint64_t w, uint64_t wp, uint64_t p) {
   const uint64_t q = (uint64_t)(((u128)wp * t) >> 64);
-  *x = s;
-  *y = w * t - q * (p2 >> 1);
+  return w * t - q * p;
+}
+
+/* Algorithm 2 (fully reducing): X, Y in [0,p) -> X + Y mod p and W (X - Y) mod p.
+ * The difference is taken mod p as the smaller of X - Y and X - Y + p (wrapping
+ * arithmetic), the product is reduced once more from [0,2p). */
+static inline void bfly2(uint64_t *x, uint64_t *y, uint64_t w, uint64_t wp, uint64_t p) {
+  const uint64_t d = *x - *y, dp = d + p;
+  const uint64_t diff = dp < d ? dp : d;
+  *x = csub64(*x + *y, p);
+  *y = csub64(shoup64(diff, w, wp, p), p);
+}
+
+/* Algorithm 3 (lazy): X, Y in [0,2p) -> X + Y and W (X - Y), both kept in [0,2p)
+ * (p < 2^62): one conditional subtraction of 2p from the sum, none after the
+ * product, whose input X - Y + 2p lies in (0, 4p). */
+static inline void bfly3(uint64_t *x, uint64_t *y, uint64_t w, uint64_t wp, uint64_t p2) {
+  const uint64_t t = *x - *y + p2;
+  *x = csub64(*x + *y, p2);
+  *y = shoup64(t, w, wp, p2 >> 1);
 }
 
 /* One forward transform in place with Algorithm `alg` (2 or 3); lazy results
