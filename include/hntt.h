@@ -287,11 +287,14 @@ int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flag
 
 /* ---------------------------------------------------------------------------
  * Schedule tuning.  A transform of length 2^l above the one-workgroup limit
- * runs as a column pass and a row pass; g_cols / g_rows are the sub-transforms
- * (columns / rows) one workgroup owns in each, and batch_chunk the number of
- * transforms that go through all passes before the next chunk starts (so a
- * chunk's intermediate result can stay in the last-level cache).  Fields set
- * to 0 keep the built-in choice.  hntt_set_tuning overrides the schedule for
+ * runs as a column pass and a row pass (an R x C view, l = log R + log C): the
+ * first log R stages of Algorithm 1 (Section 1) are fused into the column pass
+ * and the last row_log2 = log C into the row pass.  g_cols / g_rows are the
+ * sub-transforms (columns / rows) one workgroup owns in each, and batch_chunk
+ * the number of transforms that go through all passes before the next chunk
+ * starts (so a chunk's intermediate result can stay in the last-level cache).
+ * Fields set to 0 keep the built-in choice (row_log2: ceil(l / 2); both passes
+ * must stay within 1..12 stages).  hntt_set_tuning overrides the schedule for
  * (log2_len, word_bits) on this context (EINVAL if a value does not fit the
  * kernels: powers of two, thread and LDS limits, batch_chunk <= 64);
  * hntt_get_plan reports the schedule in effect.  Results never depend on the
@@ -303,7 +306,7 @@ typedef struct {
   uint32_t g_cols;
   uint32_t g_rows;
   uint32_t batch_chunk;
-  uint32_t reserved; /* must be 0 */
+  uint32_t row_log2;
 } hntt_tuning;
 int hntt_set_tuning(hntt_ctx *ctx, const hntt_tuning *t);
 int hntt_get_plan(hntt_ctx *ctx, uint32_t log2_len, uint32_t word_bits, hntt_tuning *out);
@@ -314,7 +317,10 @@ int hntt_get_plan(hntt_ctx *ctx, uint32_t log2_len, uint32_t word_bits, hntt_tun
  * hntt_trace_read waits for the pending events and writes, as JSON text,
  * {"<kernel>": {"launches": n, "total_ms": t}, ...} accumulated since the last
  * reset into buf (capacity *len bytes); *len receives the size needed.  Kernel
- * names are <pass>_<fwd|inv>_<lazy|plain>_u<bits>_n<log2 sub-length>.
+ * names are <pass>_<fwd|inv|fwdmulinv>_<lazy|plain|mont>_u<bits>_n<log2 sub-length>
+ * (fwdmulinv: a product's fused forward pass, pointwise product and first
+ * inverse pass) for transform passes, and poly_prep, poly_crt, big_crt and
+ * big_carry for the product kernels.
  * Errors: EINVAL; ENOMEM when buf is NULL or too small; EDEVICE.
  * ------------------------------------------------------------------------- */
 int hntt_trace_enable(hntt_ctx *ctx, int enable);

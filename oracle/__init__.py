@@ -20,7 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ntt_oracle.c")
-_LIB = os.path.join(_HERE, "libntt_oracle.so")
+# ORACLE_LIB: another build of the oracle (e.g. one with sanitizers)
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "libntt_oracle.so")
 
 _u64 = ctypes.c_uint64
 _p64 = ctypes.POINTER(ctypes.c_uint64)

@@ -1,13 +1,13 @@
 """Schedule autotuner for the transform passes.
 
 For a (length, word size, batch) shape it times forward+inverse transforms on
-the GPU under every legal schedule in a small search space (columns per
-workgroup in the column pass, rows per workgroup in the row pass, transforms
-per chunk) and installs the fastest one on the context with
-``Context.set_tuning``.  ``tune_polymul`` does the same per length class of a batch of
+the GPU under every legal schedule in a small search space (how Algorithm 1's
+stages are split between the column and the row pass, columns per workgroup in
+the column pass, rows per workgroup in the row pass, transforms per chunk) and
+installs the fastest one on the context with ``Context.set_tuning``.  ``tune_polymul`` does the same per length class of a batch of
 exact products, timing the whole batch plan.  The GPU is kept busy for a second before the first
-trial, and the six fastest candidates are timed again in turn, three times
-each, and ranked by their median.  Results are cached in a JSON file keyed by the GPU's compute-unit
+trial, and the six fastest candidates are timed again in turn, five times
+each over 20 repetitions, and ranked by their median.  Results are cached in a JSON file keyed by the GPU's compute-unit
 count, memory size and the shape (``$HNTT_TUNE_CACHE``, default ``~/.cache/hntt/tune.json``).  The
 schedule never changes results, only speed.
 
@@ -27,7 +27,7 @@ import torch
 from . import hntt
 
 CACHE = os.environ.get("HNTT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hntt", "tune.json"))
-REFINE_TOP, REFINE_ROUNDS = 6, 3
+REFINE_TOP, REFINE_ROUNDS, REFINE_REPS = 6, 5, 20
 SPACE = {"g_cols": [4, 8, 16, 32, 64], "g_rows": [1, 2, 4, 8, 16, 32, 64], "batch_chunk": [8, 16, 32, 64]}
 
 
@@ -85,18 +85,49 @@ def warm(ctx, x, p, w, policy, seconds):
         torch.cuda.synchronize()
 
 
+def splits(ctx, log2_len, word_bits):
+    """Row-pass lengths to try: the built-in split of the stages and one stage either way
+    (the library refuses splits that leave a pass too long or empty); [0] for one pass."""
+    ctx.set_tuning(log2_len, word_bits)
+    c0 = ctx.get_plan(log2_len, word_bits)["row_log2"]
+    if not c0:
+        return [0]
+    out = []
+    for c in (c0, c0 - 1, c0 + 1):
+        try:
+            ctx.set_tuning(log2_len, word_bits, row_log2=c)
+        except hntt.HnttError:
+            continue
+        out.append(c)
+    ctx.set_tuning(log2_len, word_bits)
+    return out
+
+
+def _apply(ctx, log2_len, word_bits, cand):
+    ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"], cand.get("row_log2", 0))
+
+
 def candidates(ctx, log2_len, word_bits, batch):
     """Legal schedules of the search space (the library rejects the others)."""
     out = []
-    for gc, gr, ch in itertools.product(SPACE["g_cols"], SPACE["g_rows"], SPACE["batch_chunk"]):
-        if ch > max(batch, 8) * 2:
-            continue
-        try:
-            ctx.set_tuning(log2_len, word_bits, gc, gr, ch)
-        except hntt.HnttError:
-            continue
-        out.append({"g_cols": gc, "g_rows": gr, "batch_chunk": ch})
-    ctx.set_tuning(log2_len, word_bits, 0, 0, 0)
+    for c in splits(ctx, log2_len, word_bits):
+        # the split's own default schedule first (it may lie outside SPACE, e.g. one
+        # column per workgroup for a long column pass of 64-bit words)
+        ctx.set_tuning(log2_len, word_bits, row_log2=c)
+        d = ctx.get_plan(log2_len, word_bits)
+        combos = [(d["g_cols"], d["g_rows"], d["batch_chunk"])]
+        combos += [k for k in itertools.product(SPACE["g_cols"], SPACE["g_rows"], SPACE["batch_chunk"])
+                   if k != combos[0]]
+        for gc, gr, ch in combos:
+            if ch > max(batch, 8) * 2 and (gc, gr, ch) != combos[0]:
+                continue
+            cand = {"g_cols": gc, "g_rows": gr, "batch_chunk": ch, "row_log2": c}
+            try:
+                _apply(ctx, log2_len, word_bits, cand)
+            except hntt.HnttError:
+                continue
+            out.append(cand)
+    ctx.set_tuning(log2_len, word_bits)
     return out
 
 
@@ -111,8 +142,7 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
     key = _key(log2_len, word_bits, batch, policy)
     cache = load_cache() if use_cache else {}
     if key in cache:
-        best = cache[key]["best"]
-        ctx.set_tuning(log2_len, word_bits, best["g_cols"], best["g_rows"], best["batch_chunk"])
+        _apply(ctx, log2_len, word_bits, cache[key]["best"])
         return cache[key]
     ctx.set_tuning(log2_len, word_bits, 0, 0, 0)
     default = dict(ctx.get_plan(log2_len, word_bits))
@@ -120,7 +150,7 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
     t0 = time.time()
     warm(ctx, x, p, omega, policy, 1.0)
     for cand in candidates(ctx, log2_len, word_bits, batch):
-        ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
+        _apply(ctx, log2_len, word_bits, cand)
         ms = _time(ctx, x, p, omega, policy, reps)
         trials.append({**cand, "ms": ms})
         if verbose:
@@ -131,14 +161,14 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
     runs = {i: [] for i in range(len(finalists))}
     for _ in range(REFINE_ROUNDS):
         for i, cand in enumerate(finalists):
-            ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
-            runs[i].append(_time(ctx, x, p, omega, policy, reps))
+            _apply(ctx, log2_len, word_bits, cand)
+            runs[i].append(_time(ctx, x, p, omega, policy, max(reps, REFINE_REPS)))
     for i, cand in enumerate(finalists):
         cand["ms"] = statistics.median(runs[i])
         if verbose:
             print(f"  finalist {cand}", flush=True)
     best = min(finalists, key=lambda r: r["ms"]) if finalists else {**default, "ms": None}
-    ctx.set_tuning(log2_len, word_bits, best["g_cols"], best["g_rows"], best["batch_chunk"])
+    _apply(ctx, log2_len, word_bits, best)
     rec = {"best": best, "default": default, "trials": len(trials), "tune_s": time.time() - t0}
     if use_cache:
         cache[key] = rec
@@ -159,13 +189,14 @@ def _plan_ms(plan, reps):
 
 def tune_polymul(ctx, pairs, outs, plain: bool = False, reps: int = 3, verbose: bool = False,
                  big: bool = False) -> dict:
-    """Pick and install, length class by length class, the (columns, rows) per workgroup of the
-    two-pass transforms of a batch of exact products (`Context.polymul_plan` arguments, or
-    `Context.bigmul_plan` ones with big=True), by timing the whole batch plan: its passes
-    differ from standalone transforms (zero upper halves read as zero, the fused pointwise
-    product, three primes per launch).  Candidates are the default schedule and its
-    neighbours; classes are taken largest first, each with the others fixed; one-pass
-    classes have nothing to tune."""
+    """Pick and install, length class by length class, the split of the stages between the two
+    passes and the (columns, rows) per workgroup of the two-pass transforms of a batch of exact
+    products (`Context.polymul_plan` arguments, or `Context.bigmul_plan` ones with big=True), by
+    timing the whole batch plan: its passes differ from standalone transforms (zero upper halves
+    read as zero, the fused product and inverse pass, three primes per launch).  Candidates are,
+    for the built-in split and one stage either way, that split's default schedule and its
+    neighbours; classes are taken largest first, each with the others fixed; one-pass classes
+    have nothing to tune."""
     make = ctx.bigmul_plan if big else ctx.polymul_plan
     classes = sorted({max(1, (max(a.numel(), b.numel()) - 1).bit_length() + 1) for a, b in pairs}, reverse=True)
     chosen = {}
@@ -175,35 +206,38 @@ def tune_polymul(ctx, pairs, outs, plain: bool = False, reps: int = 3, verbose: 
         plan.execute()
     plan.destroy()
     for l in classes:
-        ctx.set_tuning(l, 32, 0, 0, 0)
+        ctx.set_tuning(l, 32)
         default = ctx.get_plan(l, 32)
         if not default["g_cols"]:
             continue  # one pass
-        # the default and its neighbours: a quarter, half and twice its columns or rows
-        # per workgroup (the library refuses those that do not fit)
+        # per split: its default schedule and the neighbours, a quarter, half and twice its
+        # columns or rows per workgroup (the library refuses those that do not fit)
         cands = []
-        for gc in (default["g_cols"] // 4, default["g_cols"] // 2, default["g_cols"], default["g_cols"] * 2):
-            for gr in (default["g_rows"] // 4, default["g_rows"] // 2, default["g_rows"], default["g_rows"] * 2):
-                if gc < 1 or gr < 1 or (gc, gr) in cands:
-                    continue
-                try:
-                    ctx.set_tuning(l, 32, gc, gr, 0)
-                except hntt.HnttError:
-                    continue
-                cands.append((gc, gr))
+        for c in splits(ctx, l, 32):
+            ctx.set_tuning(l, 32, row_log2=c)
+            d = ctx.get_plan(l, 32)
+            for gc in (d["g_cols"] // 4, d["g_cols"] // 2, d["g_cols"], d["g_cols"] * 2):
+                for gr in (d["g_rows"] // 4, d["g_rows"] // 2, d["g_rows"], d["g_rows"] * 2):
+                    if gc < 1 or gr < 1 or (c, gc, gr) in cands:
+                        continue
+                    try:
+                        ctx.set_tuning(l, 32, gc, gr, 0, c)
+                    except hntt.HnttError:
+                        continue
+                    cands.append((c, gc, gr))
         times = {}
         for rnd in range(2):  # all once, then the three fastest again
-            pool = cands if rnd == 0 else sorted(cands, key=lambda c: statistics.median(times[c]))[:3]
-            for gc, gr in pool:
-                ctx.set_tuning(l, 32, gc, gr, 0)
+            pool = cands if rnd == 0 else sorted(cands, key=lambda k: statistics.median(times[k]))[:3]
+            for c, gc, gr in pool:
+                ctx.set_tuning(l, 32, gc, gr, 0, c)
                 plan = make(pairs, outs, plain=plain)
                 plan.execute()
-                times.setdefault((gc, gr), []).append(_plan_ms(plan, reps))
+                times.setdefault((c, gc, gr), []).append(_plan_ms(plan, reps))
                 plan.destroy()
-        best = min(times, key=lambda c: statistics.median(times[c]))
-        ctx.set_tuning(l, 32, best[0], best[1], 0)
-        chosen[l] = {"g_cols": best[0], "g_rows": best[1], "ms": statistics.median(times[best]),
-                     "default": {"g_cols": default["g_cols"], "g_rows": default["g_rows"]}}
+        best = min(times, key=lambda k: statistics.median(times[k]))
+        ctx.set_tuning(l, 32, best[1], best[2], 0, best[0])
+        chosen[l] = {"row_log2": best[0], "g_cols": best[1], "g_rows": best[2], "ms": statistics.median(times[best]),
+                     "default": {k: default[k] for k in ("row_log2", "g_cols", "g_rows")}}
         if verbose:
             print(f"  class 2^{l}: {chosen[l]}", flush=True)
     return {"classes": chosen, "tune_s": time.time() - t0}

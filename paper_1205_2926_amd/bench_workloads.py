@@ -139,7 +139,7 @@ def polymul(args):
         ms = _events_ms(plan.execute, max(3, args.steps // 2))
         res["plain" if plain else "lazy"] = {"ms_per_batch": ms, "products_per_s": len(pairs) / (ms / 1e3),
                                              "butterflies_per_s": bfly / (ms / 1e3),
-                                             "schedules": {f"2^{l}": {k: v[k] for k in ("g_cols", "g_rows")}
+                                             "schedules": {f"2^{l}": {k: v[k] for k in ("row_log2", "g_cols", "g_rows")}
                                                            for l, v in tuned["classes"].items()},
                                              "tune_s": tuned["tune_s"]}
         plan.destroy()
@@ -228,7 +228,7 @@ def bigmul(args):
         torch.cuda.synchronize()
         ms = _events_ms(plan.execute, max(3, args.steps // 2))
         res[policy] = {"ms_per_batch": ms, "products_per_s": count / (ms / 1e3),
-                       "schedules": {f"2^{l}": {k: v[k] for k in ("g_cols", "g_rows")}
+                       "schedules": {f"2^{l}": {k: v[k] for k in ("row_log2", "g_cols", "g_rows")}
                                      for l, v in tuned["classes"].items()}}
         plan.destroy()
     for i in (0, count - 1):

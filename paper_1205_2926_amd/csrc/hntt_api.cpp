@@ -117,7 +117,7 @@ int check_desc(hntt_ctx *ctx, const hntt_desc &d, uint32_t flags) {
   return HNTT_OK;
 }
 
-Plan make_plan(int l, int word_bits) {
+Plan make_plan(int l, int word_bits, int row_log2) {
   Plan pl{};
   const int lmax = max_whole_log(word_bits);
   if (l <= lmax) {
@@ -128,7 +128,7 @@ Plan make_plan(int l, int word_bits) {
     return pl;
   }
   pl.split = true;
-  pl.c = (l + 1) / 2;
+  pl.c = row_log2 ? row_log2 : (l + 1) / 2;
   pl.r = l - pl.c;
   auto lds_ok = [&](int n, int g) {
     PassParams pp{};
@@ -160,9 +160,14 @@ int check_tuning(const hntt_tuning &t, std::string *why) {
   if (t.word_bits != 32 && t.word_bits != 64) return fail("word_bits must be 32 or 64");
   const int lmax = max_whole_log((int)t.word_bits);
   if (t.log2_len < 1 || (int)t.log2_len > 2 * lmax) return fail("log2_len outside the two-pass range");
-  if (t.reserved) return fail("reserved must be 0");
   if (t.batch_chunk > (uint32_t)kMaxBatchPerLaunch) return fail("batch_chunk above the per-launch limit");
-  const Plan base = make_plan((int)t.log2_len, (int)t.word_bits);
+  if (t.row_log2) {
+    if ((int)t.log2_len <= lmax) return fail("row_log2 applies to two-pass lengths only");
+    if ((int)t.row_log2 > kMaxPassLog || (int)t.log2_len - (int)t.row_log2 < 1 ||
+        (int)t.log2_len - (int)t.row_log2 > kMaxPassLog)
+      return fail("row_log2 must leave both passes 1..12 stages");
+  }
+  const Plan base = make_plan((int)t.log2_len, (int)t.word_bits, (int)t.row_log2);
   auto pow2 = [](uint32_t v) { return v && !(v & (v - 1)); };
   auto fits = [&](PassKind kind, int n, uint32_t g) {
     PassParams pp{};
@@ -185,8 +190,8 @@ int check_tuning(const hntt_tuning &t, std::string *why) {
 }
 
 Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits) {
-  Plan pl = make_plan(l, word_bits);
   auto it = ctx->tuning.find(std::make_pair(l, word_bits));
+  Plan pl = make_plan(l, word_bits, it != ctx->tuning.end() ? (int)it->second.row_log2 : 0);
   if (it != ctx->tuning.end()) {
     if (it->second.g_cols) pl.g_cols = (int)it->second.g_cols;
     if (it->second.g_rows) pl.g_rows = (int)it->second.g_rows;
@@ -281,21 +286,22 @@ int upload(hntt_ctx *ctx, PendingUploads &pend, const std::vector<uint64_t> &src
   return HNTT_OK;
 }
 
-const Tables *find_tables(const hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont) {
-  auto it = ctx->tables.find(std::make_tuple(p, omega, l, bits, mont));
+const Tables *find_tables(const hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, int row_log2) {
+  auto it = ctx->tables.find(std::make_tuple(p, omega, l, bits, mont, make_plan(l, bits, row_log2).c));
   return it == ctx->tables.end() ? nullptr : &it->second;
 }
 
 // Twiddle tables for one (p, omega, l, word_bits, form): built on the host once and kept on the device.
-int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, const Tables **out) {
-  const auto key = std::make_tuple(p, omega, l, bits, mont);
+int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, int row_log2,
+               const Tables **out) {
+  const auto key = std::make_tuple(p, omega, l, bits, mont, make_plan(l, bits, row_log2).c);
   auto it = ctx->tables.find(key);
   if (it != ctx->tables.end()) {
     *out = &it->second;
     return HNTT_OK;
   }
   Tables t{};
-  t.plan = make_plan(l, bits);
+  t.plan = make_plan(l, bits, row_log2);
   t.mont = mont;
   const TableForm form(p, bits, mont);
   const uint64_t omega_inv = powmod(omega, p - 2, p);
@@ -322,34 +328,41 @@ int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool 
     if ((rc = table(powmod(omega_inv, C, p), r, &t.inv))) return rc;
     if ((rc = table(powmod(omega, R, p), c, &t.row_fwd))) return rc;
     if ((rc = table(powmod(omega_inv, R, p), c, &t.row_inv))) return rc;
-    // Split twiddles as two factors per sub-transform (see Edge in ntt_pass.hip).
-    // Forward, applied on load in the row pass: row B (s = rev_r(B)) needs
-    // omega^(s pos) = omega^(s lo) * omega^(s hi 2^sf) with pos = hi 2^sf + lo, where
-    // sf = c - KH(c) is the boundary of the row pass's first register round.
-    // Inverse, applied on load in the column pass: column col needs
-    // L^-1 omega^(-col rev_r(pos)) with rev_r(pos) = rev_si(lo) 2^(r-si) + rev_(r-si)(hi),
-    // si = KL(r).  Each sub-transform's factors are [lo factors | hi factors].
-    const RoundSplit rs_c = pass_split(c, bits), rs_r = pass_split(r, bits);
-    const int sf = c - rs_c.kh, si = rs_r.kl;
-    const uint64_t Sf = (1ull << sf) + (1ull << (c - sf)), Si = (1ull << si) + (1ull << (r - si));
-    std::vector<uint64_t> f(form.words() * R * Sf), iv(form.words() * C * Si);
+    // Split twiddles, one row-major table per direction (see Edge in ntt_pass.hip).
+    // Row B (s = rev_r(B)) needs, at row position pos = hi 2^sf + lo, the factor
+    // omega^(s pos) (forward, applied as the row pass loads the word) or
+    // L^-1 omega^(-s pos) (inverse, applied as the row pass stores it), where
+    // sf = c - KH(c) is the boundary of the row pass's high register round.  Each
+    // row holds [low factors z^lo | high factors z^(hi 2^sf) (times L^-1 in the
+    // inverse) | folded low factors z^lo W(lo)], z = omega^(+-s), W(lo) being the
+    // twiddle of the row-transform stage that pairs bit sf at index lo,
+    // (omega^(+-R))^(lo 2^(c-1-sf)): the low factor is folded into that stage (Fold
+    // in ntt_pass.hip).
+    const RoundSplit rs_c = pass_split(c, bits);
+    const int sf = c - rs_c.kh;
+    const uint64_t Sf = 2 * (1ull << sf) + (1ull << (c - sf));
+    std::vector<uint64_t> f(form.words() * R * Sf), iv(form.words() * R * Sf);
     auto put = [&](std::vector<uint64_t> &v, uint64_t idx, uint64_t w) { form.put(v, idx, w); };
-    for (uint64_t B = 0; B < R; ++B) {
-      const uint64_t ws = powmod(omega, bitrev((unsigned)B, r), p);  // omega^s
-      const uint64_t wsh = powmod(ws, 1ull << sf, p);                 // omega^(s 2^sf)
-      uint64_t x = 1;
-      for (uint64_t lo = 0; lo < (1ull << sf); ++lo, x = mulmod(x, ws, p)) put(f, B * Sf + lo, x);
-      x = 1;
-      for (uint64_t hi = 0; hi < (1ull << (c - sf)); ++hi, x = mulmod(x, wsh, p)) put(f, B * Sf + (1ull << sf) + hi, x);
-    }
-    // (the inverse table is factor-major, [factor][column], so that the adjacent
-    // columns of a workgroup read adjacent entries)
-    for (uint64_t col = 0; col < C; ++col) {
-      const uint64_t wc = powmod(omega_inv, col, p);  // omega^(-col)
-      for (uint64_t lo = 0; lo < (1ull << si); ++lo)
-        put(iv, lo * C + col, powmod(wc, (uint64_t)bitrev((unsigned)lo, si) << (r - si), p));
-      for (uint64_t hi = 0; hi < (1ull << (r - si)); ++hi)
-        put(iv, ((1ull << si) + hi) * C + col, mulmod(linv, powmod(wc, bitrev((unsigned)hi, r - si), p), p));
+    const uint64_t w_row[2] = {powmod(omega, R, p), powmod(omega_inv, R, p)};
+    for (int dir = 0; dir < 2; ++dir) {
+      std::vector<uint64_t> &dst = dir ? iv : f;
+      const uint64_t root = dir ? omega_inv : omega;
+      const uint64_t hscale = dir ? linv : 1;
+      // twiddle step of the stage pairing bit sf (used only when the row pass has two rounds)
+      const uint64_t wstage = sf < c ? powmod(w_row[dir], 1ull << (c - 1 - sf), p) : 1;
+      for (uint64_t B = 0; B < R; ++B) {
+        const uint64_t ws = powmod(root, bitrev((unsigned)B, r), p);  // z = omega^(+-s)
+        const uint64_t wsh = powmod(ws, 1ull << sf, p);                // z^(2^sf)
+        const uint64_t fold0 = B * Sf + (1ull << sf) + (1ull << (c - sf));
+        uint64_t x = 1, ws_lo = 1;
+        for (uint64_t lo = 0; lo < (1ull << sf); ++lo, x = mulmod(x, ws, p), ws_lo = mulmod(ws_lo, wstage, p)) {
+          put(dst, B * Sf + lo, x);
+          put(dst, fold0 + lo, mulmod(x, ws_lo, p));
+        }
+        x = hscale;
+        for (uint64_t hi = 0; hi < (1ull << (c - sf)); ++hi, x = mulmod(x, wsh, p))
+          put(dst, B * Sf + (1ull << sf) + hi, x);
+      }
     }
     if ((rc = upload(ctx, pend, f, bits, &t.tt_fwd))) return rc;
     if ((rc = upload(ctx, pend, iv, bits, &t.tt_inv))) return rc;
@@ -374,7 +387,8 @@ std::string pass_name(const PassParams &pp) {
   const char *kind = pp.kind == PassKind::kWhole ? "whole" : pp.kind == PassKind::kRows ? "rows" : "cols";
   char buf[96];
   const char *pol = pp.policy == kPolicyMont ? "mont" : pp.policy == kPolicyLazy ? "lazy" : "plain";
-  snprintf(buf, sizeof buf, "%s_%s_%s_u%d_n%d", kind, pp.inverse ? "inv" : "fwd", pol, pp.word_bits, pp.n);
+  const char *dir = pp.fuse_inverse ? "fwdmulinv" : pp.inverse ? "inv" : "fwd";
+  snprintf(buf, sizeof buf, "%s_%s_%s_u%d_n%d", kind, dir, pol, pp.word_bits, pp.n);
   return buf;
 }
 
@@ -436,13 +450,13 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const Plan &plan, const std::v
     cols.log_other = plan.c;
     cols.group = plan.g_cols;
     cols.tw = inverse ? t.inv : t.fwd;
-    cols.tt = inverse ? t.tt_inv : nullptr;  // the split twiddle enters with the second pass
+    cols.tt = nullptr;  // the split twiddle belongs to the row pass (both directions)
     rows.kind = PassKind::kRows;
     rows.n = plan.c;
     rows.log_other = plan.r;
     rows.group = plan.g_rows;
     rows.tw = inverse ? t.row_inv : t.row_fwd;
-    rows.tt = inverse ? nullptr : t.tt_fwd;
+    rows.tt = inverse ? t.tt_inv : t.tt_fwd;
     if (!inverse) {
       cols.normalize = false;
       rows.normalize = norm;
@@ -523,7 +537,8 @@ int transform(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flags, v
     const uint64_t p = std::get<0>(kv.first), omega = std::get<1>(kv.first);
     const int l = std::get<2>(kv.first), bits = std::get<3>(kv.first);
     const Tables *t = nullptr;
-    if ((rc = get_tables(ctx, p, omega, l, bits, (flags & HNTT_MONT) != 0, &t))) return rc;
+    if ((rc = get_tables(ctx, p, omega, l, bits, (flags & HNTT_MONT) != 0, effective_plan(ctx, l, bits).c, &t)))
+      return rc;
     const Plan plan = effective_plan(ctx, l, bits);
     if ((rc = run_transform(ctx, *t, plan, kv.second, p, l, bits, inverse, flags, (hipStream_t)stream))) return rc;
   }
@@ -648,7 +663,7 @@ int hntt_get_plan(hntt_ctx *ctx, uint32_t log2_len, uint32_t word_bits, hntt_tun
   out->g_cols = pl.split ? (uint32_t)pl.g_cols : 0;
   out->g_rows = pl.split ? (uint32_t)pl.g_rows : 0;
   out->batch_chunk = (uint32_t)pl.chunk;
-  out->reserved = 0;
+  out->row_log2 = (uint32_t)pl.c;
   return HNTT_OK;
 }
 

@@ -69,7 +69,8 @@ struct hntt_ctx {
   bool device_ready = false;
   std::string last_error;
   std::map<uint64_t, bool> prime_cache;
-  std::map<std::tuple<uint64_t, uint64_t, int, int, bool>, hntt::Tables> tables;
+  // (p, omega, l, word bits, Montgomery form, row-pass length c) -> resident tables
+  std::map<std::tuple<uint64_t, uint64_t, int, int, bool, int>, hntt::Tables> tables;
   std::map<std::pair<int, int>, hntt_tuning> tuning;  // (log2_len, word_bits) -> schedule override
   std::vector<std::unique_ptr<hntt::DeviceBuffer>> buffers;
   hntt_polymul_plan *poly_cache = nullptr;  // last plan of hntt_polymul_crt
@@ -93,13 +94,16 @@ struct hntt_ctx {
 
 namespace hntt {
 int check_desc(hntt_ctx *ctx, const hntt_desc &d, uint32_t flags);
-Plan make_plan(int l, int word_bits);
+// row_log2: the row pass's stages (0: the built-in ceil(l / 2)).
+Plan make_plan(int l, int word_bits, int row_log2 = 0);
 Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits);
 int check_tuning(const hntt_tuning &t, std::string *why);
 int ensure_device(hntt_ctx *ctx);
-int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, const Tables **out);
+// Tables for the split of make_plan(l, bits, row_log2).
+int get_tables(hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, int row_log2,
+               const Tables **out);
 // The resident tables of (p, omega, l, bits, form), or null; builds nothing.
-const Tables *find_tables(const hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont);
+const Tables *find_tables(const hntt_ctx *ctx, uint64_t p, uint64_t omega, int l, int bits, bool mont, int row_log2);
 // Launch wrappers that record HIP events around the launch when tracing is on
 // (hntt_trace_*): any launch under a kernel name, or one NTT pass under its name.
 struct PassParams;

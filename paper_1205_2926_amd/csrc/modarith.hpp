@@ -48,33 +48,42 @@ __device__ __forceinline__ T csub(T x, T m) {
   return d < x ? d : x;
 }
 
+// -p mod 2^32 for the multiply-add below, behind an empty asm statement so that the
+// compiler cannot see it is a negation (it would otherwise rewrite Q (beta - p) + W t
+// as W t - Q p: two low products and a subtraction).  The statement has no side
+// effects, so the compiler computes it once per kernel (one vector register).
+__device__ __forceinline__ uint32_t opaque_neg_u32(uint32_t p) {
+  uint32_t np = 0u - p;
+  asm("; -p %0" : "+v"(np));
+  return np;
+}
+
 // Shoup's product by a constant (Algorithm 2, estimated quotient then two
 // low products): for any 0 <= t < beta and W' = floor(W beta / p),
 // W t - Q p lies in [0, 2p) (Theorem 1), so no correction is applied here.
+// On 32-bit words the low words come from one v_mul_lo_u32 (W t) and one
+// v_mad_u64_u32: Q (beta - p) + W t, whose low word is W t - Q p mod beta.
 template <class Wd>
 __device__ __forceinline__ typename Wd::T shoup_lazy(typename Wd::T t, typename Wd::T w, typename Wd::T wp,
                                                      typename Wd::T p) {
-  const typename Wd::T q = Wd::mulhi(wp, t);
-  return Wd::mullo(w, t) - Wd::mullo(q, p);
-}
-
-// The same product with its low words taken from v_mad_u64_u32 (32x32+64 -> 64):
-// W t from one multiply-add with a zero addend, then W t + Q (beta - p), whose low
-// word is W t - Q p mod beta; two instructions where shoup_lazy issues two low
-// products and a subtraction.  64-bit words use shoup_lazy's form.  The forward
-// passes use it; the inverse passes measured slower with it and keep shoup_lazy.
-template <class Wd>
-__device__ __forceinline__ typename Wd::T shoup_lazy_mad(typename Wd::T t, typename Wd::T w, typename Wd::T wp,
-                                                         typename Wd::T p) {
   if constexpr (Wd::kBits == 32) {
     const uint32_t q = Wd::mulhi(wp, t);
-    uint64_t wt, r, c0, c1;  // c0, c1: the instruction's carry-out, unused
-    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(wt), "=s"(c0) : "v"(w), "v"(t));
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(c1) : "v"(q), "v"(0u - p), "v"(wt));
-    return (uint32_t)r;
+    const uint32_t wt = w * t;
+    return (uint32_t)((uint64_t)q * opaque_neg_u32(p) + wt);
   } else {
-    return shoup_lazy<Wd>(t, w, wp, p);
+    const typename Wd::T q = Wd::mulhi(wp, t);
+    return Wd::mullo(w, t) - Wd::mullo(q, p);
   }
+}
+
+// The same product with the low words from two v_mul_lo_u32 and a subtraction
+// (Algorithm 2's steps as written).  The inverse passes use this form: with the
+// multiply-add form their row and column passes measured slower.
+template <class Wd>
+__device__ __forceinline__ typename Wd::T shoup_lazy_sub(typename Wd::T t, typename Wd::T w, typename Wd::T wp,
+                                                         typename Wd::T p) {
+  const typename Wd::T q = Wd::mulhi(wp, t);
+  return Wd::mullo(w, t) - Wd::mullo(q, p);
 }
 
 // Montgomery's product (the multiplication of Algorithm 5): for 0 <= t < beta,
@@ -100,7 +109,7 @@ __device__ __forceinline__ void bfly_fwd_lazy(typename Wd::T &x, typename Wd::T 
   using T = typename Wd::T;
   const T s = csub<T>(x + y, p2);
   const T t = x - y + p2;
-  y = shoup_lazy_mad<Wd>(t, w, wp, p);
+  y = shoup_lazy<Wd>(t, w, wp, p);
   x = s;
 }
 
@@ -138,7 +147,7 @@ __device__ __forceinline__ void bfly_fwd_plain(typename Wd::T &x, typename Wd::T
   T d = x - y;
   const T dp = d + p;
   d = dp < d ? dp : d;
-  y = csub<T>(shoup_lazy_mad<Wd>(d, w, wp, p), p);
+  y = csub<T>(shoup_lazy<Wd>(d, w, wp, p), p);
   x = s;
 }
 
@@ -159,7 +168,7 @@ __device__ __forceinline__ void bfly_inv_lazy(typename Wd::T &x, typename Wd::T 
                                               typename Wd::T wp, typename Wd::T p, typename Wd::T p2) {
   using T = typename Wd::T;
   const T xr = csub<T>(x, p2);
-  const T t = shoup_lazy<Wd>(y, w, wp, p);
+  const T t = shoup_lazy_sub<Wd>(y, w, wp, p);
   x = xr + t;
   y = xr - t + p2;
 }
@@ -194,7 +203,7 @@ template <class Wd>
 __device__ __forceinline__ void bfly_inv_plain(typename Wd::T &x, typename Wd::T &y, typename Wd::T w,
                                                typename Wd::T wp, typename Wd::T p) {
   using T = typename Wd::T;
-  const T t = csub<T>(shoup_lazy<Wd>(y, w, wp, p), p);
+  const T t = csub<T>(shoup_lazy_sub<Wd>(y, w, wp, p), p);
   const T s = csub<T>(x + t, p);
   T d = x - t;
   const T dp = d + p;

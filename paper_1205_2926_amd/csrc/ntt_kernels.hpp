@@ -41,6 +41,10 @@ struct SlotParams {
   uint64_t scale_wp;  // and its Shoup constant (unused by the Montgomery policy)
   uint64_t jinv;      // p^-1 mod beta (Montgomery policy; fused pointwise product)
   uint64_t r2;        // beta^2 mod p (fused pointwise product)
+  // fused forward + inverse launch (PassParams::fuse_inverse): the inverse
+  // transform's per-stage table and split-twiddle factors of the same sub-transform
+  const void *tw2;
+  const void *tt2;
 };
 
 // Which pass of the transform a launch performs.
@@ -123,6 +127,12 @@ struct PassParams {
   // (this transform's own words are left stale).  Used by the polynomial product:
   // B_k's last pass multiplies into A_k.
   uint32_t pm_off;
+  // With pm_off, 32-bit words, a table and a Shoup policy only: instead of writing
+  // the product, run the inverse transform's row pass (kRows) or whole transform
+  // (kWhole, times L^-1 and fully reduced when normalize is set) on it and write
+  // that over the partner (slots' tw2/tt2 tables).  The inverse row output is left
+  // in the range the following inverse column pass accepts.
+  bool fuse_inverse;
   // First forward pass only: the upper half of every input (positions >= 2^l / 2)
   // is known to be zero, so it is not read (the padded operands of a product).
   bool zero_upper;

@@ -147,12 +147,15 @@ struct Mod {
   T p, p2, j;
 };
 
-template <int Pol>
+// Direction of a butterfly, round or edge: forward (Algorithm 1, DIF butterflies)
+// or inverse (Algorithm 1 run backwards, DIT butterflies).  Kernels take this
+// file's direction (kInverse); a kernel that runs both takes each explicitly.
+template <int Pol, bool INV = kInverse>
 __device__ __forceinline__ void bfly(T &x, T &y, const TwT<Pol> &tw, const Mod &m) {
   if constexpr (Pol == kPolicyMont) {
-    if constexpr (kInverse) bfly_inv_mont<Wd>(x, y, tw, m.p, m.p2, m.j);
+    if constexpr (INV) bfly_inv_mont<Wd>(x, y, tw, m.p, m.p2, m.j);
     else bfly_fwd_mont<Wd>(x, y, tw, m.p, m.p2, m.j);
-  } else if constexpr (kInverse) {
+  } else if constexpr (INV) {
     if constexpr (Pol == kPolicyLazy) bfly_inv_lazy<Wd>(x, y, tw.x, tw.y, m.p, m.p2);
     else bfly_inv_plain<Wd>(x, y, tw.x, tw.y, m.p);
   } else {
@@ -162,9 +165,9 @@ __device__ __forceinline__ void bfly(T &x, T &y, const TwT<Pol> &tw, const Mod &
 }
 
 // Butterfly whose twiddle is 1: no product (both lazy policies share the ranges).
-template <int Pol>
+template <int Pol, bool INV = kInverse>
 __device__ __forceinline__ void bfly_w1(T &x, T &y, const Mod &m) {
-  if constexpr (kInverse) {
+  if constexpr (INV) {
     if constexpr (Pol != kPolicyPlain) bfly_inv_lazy_w1<Wd>(x, y, m.p2);
     else bfly_inv_plain_w1<Wd>(x, y, m.p);
   } else {
@@ -174,12 +177,17 @@ __device__ __forceinline__ void bfly_w1(T &x, T &y, const Mod &m) {
 }
 
 // x (any word) times a table constant, result in [0,2p).
-template <int Pol>
+template <int Pol, bool INV = kInverse>
 __device__ __forceinline__ T mul_const(T x, const TwT<Pol> &tw, const Mod &m) {
   if constexpr (Pol == kPolicyMont) return mont_lazy<Wd>(x, tw, m.p, m.j);
-  else if constexpr (!kInverse) return shoup_lazy_mad<Wd>(x, tw.x, tw.y, m.p);
-  else return shoup_lazy<Wd>(x, tw.x, tw.y, m.p);
+  else if constexpr (!INV) return shoup_lazy<Wd>(x, tw.x, tw.y, m.p);
+  else return shoup_lazy_sub<Wd>(x, tw.x, tw.y, m.p);
 }
+
+// Forward row passes: fold the split twiddle's low factor into the high round, and
+// read its high factors from the LDS row pads.
+constexpr bool kFwdFold = false;
+constexpr bool kFwdHiLds = true;
 
 // Words per 16-byte vector access.
 constexpr int kVec = 16 / sizeof(T);
@@ -203,10 +211,123 @@ struct NoHook {
   __device__ __forceinline__ void operator()() const {}
 };
 
-template <int Pol, int N_LOG, int K, bool LowRound, bool ZU = false, class Src, class Dst, class Hook = NoHook>
+// Fold of a per-thread factor A into one stage of the row pass's high round.  A
+// round's stages are linear in the thread's words, so a factor common to all of
+// them (the split twiddle's low factor, which depends only on the row and on the
+// thread's low position bits) may be applied at either end of the round and
+// merged into the stage there, whose butterflies all have the same twiddle W
+// (its index is the thread's low position bits):
+//   forward (DIF), the round's last stage: (X, Y) -> (X + Y, W (X - Y)) becomes
+//   (A (X + Y), (A W) (X - Y)), with no conditional subtraction before the
+//   product by A (a product accepts any input below beta);
+//   inverse (DIT), the round's first stage: (X, Y) -> (X + W Y, X - W Y) becomes
+//   (A X + (A W) Y, A X - (A W) Y), where the product A X also takes the place
+//   of Algorithm 4's conditional subtraction of X.
+// Either way one product by A and one by the precomputed A W replace the product
+// by W and two products by A.
+struct NoFold {
+  static constexpr bool kOn = false;
+};
+template <int Pol>
+struct Fold {
+  static constexpr bool kOn = true;
+  TwT<Pol> a, aw;
+};
+
+template <int Pol>
+__device__ __forceinline__ void bfly_fold(T &x, T &y, const TwT<Pol> &a, const TwT<Pol> &aw, const Mod &m) {
+  if constexpr (Pol == kPolicyPlain) {  // X, Y in [0,p): every output fully reduced
+    T d = x - y;
+    const T dp = d + m.p;
+    d = dp < d ? dp : d;
+    x = csub<T>(mul_const<Pol, false>(x + y, a, m), m.p);
+    y = csub<T>(mul_const<Pol, false>(d, aw, m), m.p);
+  } else {  // X, Y in [0,2p): X + Y < 4p and X - Y + 2p < 4p are below beta
+    const T t = x - y + m.p2;
+    x = mul_const<Pol, false>(x + y, a, m);
+    y = mul_const<Pol, false>(t, aw, m);
+  }
+}
+
+template <int Pol>
+__device__ __forceinline__ void bfly_fold_inv(T &x, T &y, const TwT<Pol> &a, const TwT<Pol> &aw, const Mod &m) {
+  if constexpr (Pol == kPolicyPlain) {  // X, Y in [0,p): every output fully reduced
+    const T xr = csub<T>(mul_const<Pol, true>(x, a, m), m.p);
+    const T t = csub<T>(mul_const<Pol, true>(y, aw, m), m.p);
+    T d = xr - t;
+    const T dp = d + m.p;
+    y = dp < d ? dp : d;
+    x = csub<T>(xr + t, m.p);
+  } else {  // X, Y in [0,4p) (Theorem 3 ranges); both products in [0,2p)
+    const T xr = mul_const<Pol, true>(x, a, m);
+    const T t = mul_const<Pol, true>(y, aw, m);
+    x = xr + t;
+    y = xr - t + m.p2;
+  }
+}
+
+// A source whose words are loaded raw and finished (the split twiddle applied)
+// only after the round's hook, so that the loads can be issued before a barrier
+// that the finishing step needs (its factors staged in LDS).
+template <class S, class = void>
+struct DefersIn {
+  static constexpr bool value = false;
+};
+template <class S>
+struct DefersIn<S, std::void_t<decltype(S::kDeferIn)>> {
+  static constexpr bool value = S::kDeferIn;
+};
+
+// The K stages of one round on a thread's 2^K words v (positions base | (e << b_lo)).
+template <int Pol, int N_LOG, int K, bool LowRound, bool INV, class FoldT>
+__device__ __forceinline__ void round_stages(T (&v)[1 << K], int b_lo, int base, const TwT<Pol> *tws,
+                                            const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m,
+                                            const FoldT &fold) {
+  constexpr int M = 1 << K;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int hb = INV ? s : K - 1 - s;
+#pragma unroll
+      for (int e = 0; e < M; ++e) {
+        if (e & (1 << hb)) continue;
+        if constexpr (FoldT::kOn) {
+          if (s == (INV ? 0 : K - 1)) {  // the stage pairing bit b_lo (hb = 0), the thread's factor folded in
+            if constexpr (INV) bfly_fold_inv<Pol>(v[e], v[e | 1], fold.a, fold.aw, m);
+            else bfly_fold<Pol>(v[e], v[e | 1], fold.a, fold.aw, m);
+            continue;
+          }
+        }
+        if constexpr (LowRound) {
+          const int kk = e & ((1 << hb) - 1);
+          if (kk == 0) {
+            bfly_w1<Pol, INV>(v[e], v[e | (1 << hb)], m);
+          } else {
+            const TwT<Pol> tw = twg[(1 << hb) + kk];
+            bfly<Pol, INV>(v[e], v[e | (1 << hb)], tw, m);
+          }
+        } else {
+          const int b = b_lo + hb;
+          const int pos = base | (e << b_lo);
+          const int ti = (1 << b) + (pos & ((1 << b) - 1));
+          const TwT<Pol> tw = tw_global_here(N_LOG) ? twg[ti] : tws[ti];
+          bfly<Pol, INV>(v[e], v[e | (1 << hb)], tw, m);
+        }
+      }
+    }
+}
+
+// Optional work on a round's words after its stages and before they are stored
+// (the fused pointwise product and inverse stages of a polynomial product).
+struct NoMid {
+  static constexpr bool kOn = false;
+};
+
+template <int Pol, int N_LOG, int K, bool LowRound, bool ZU = false, class Src, class Dst, class Hook = NoHook,
+          class FoldT = NoFold, bool INV = kInverse, class MidT = NoMid>
 __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol> *tws,
                                        const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m, const Src &src,
-                                       const Dst &dst, const Hook &after_load = Hook{}) {
+                                       const Dst &dst, const Hook &after_load = Hook{}, const FoldT &fold = FoldT{},
+                                       const MidT &mid = MidT{}) {
   constexpr int groups = 1 << (N_LOG - K);
   constexpr int M = 1 << K;
 #pragma unroll 1
@@ -229,6 +350,9 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
           }
         }
       }
+    } else if constexpr (DefersIn<Src>::value) {
+#pragma unroll
+      for (int e = 0; e < M; ++e) v[e] = (ZU && ((e >> (K - 1)) & 1)) ? (T)0 : src.load_raw(base, e << b_lo);
     } else {
 #pragma unroll
       for (int e = 0; e < M; ++e) v[e] = (ZU && ((e >> (K - 1)) & 1)) ? (T)0 : src.load2(base, e << b_lo);
@@ -237,31 +361,15 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
     // the workgroup is reached once by all threads.
     if (gi == t) {
       after_load();
-      if constexpr (kInverse) __builtin_amdgcn_s_setprio(0);  // raised at the start of k_pass
+      if constexpr (INV) __builtin_amdgcn_s_setprio(0);  // raised at the start of an inverse k_pass
     }
+    if constexpr (DefersIn<Src>::value) {
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-      const int hb = kInverse ? s : K - 1 - s;
-#pragma unroll
-      for (int e = 0; e < M; ++e) {
-        if (e & (1 << hb)) continue;
-        if constexpr (LowRound) {
-          const int kk = e & ((1 << hb) - 1);
-          if (kk == 0) {
-            bfly_w1<Pol>(v[e], v[e | (1 << hb)], m);
-          } else {
-            const TwT<Pol> tw = twg[(1 << hb) + kk];
-            bfly<Pol>(v[e], v[e | (1 << hb)], tw, m);
-          }
-        } else {
-          const int b = b_lo + hb;
-          const int pos = base | (e << b_lo);
-          const int ti = (1 << b) + (pos & ((1 << b) - 1));
-          const TwT<Pol> tw = tw_global_here(N_LOG) ? twg[ti] : tws[ti];
-          bfly<Pol>(v[e], v[e | (1 << hb)], tw, m);
-        }
-      }
+      for (int e = 0; e < M; ++e)
+        if (!(ZU && ((e >> (K - 1)) & 1))) v[e] = src.finish(v[e], base, e << b_lo);
     }
+    round_stages<Pol, N_LOG, K, LowRound, INV>(v, b_lo, base, tws, twg, m, fold);
+    if constexpr (MidT::kOn) mid(v, base);
     if constexpr (LowRound && Dst::kContig && M >= kVec) {
 #pragma unroll
       for (int e = 0; e < M; e += kVec) dst.store_vec(base + e, &v[e]);
@@ -273,10 +381,10 @@ __device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol>
 }
 
 // Final reduction of a lazy result: forward outputs lie in [0,2p), inverse in [0,4p).
-template <int Pol>
+template <int Pol, bool INV = kInverse>
 __device__ __forceinline__ T reduce_final(T x, T p) {
   if constexpr (Pol == kPolicyPlain) return x;
-  if constexpr (kInverse) x = csub<T>(x, p + p);
+  if constexpr (INV) x = csub<T>(x, p + p);
   return csub<T>(x, p);
 }
 
@@ -300,16 +408,65 @@ __device__ __forceinline__ T pmul_word(T a, T b, const Mod &m, T r2) {
   return csub<T>(mont_lazy<Wd>(u, r2, m.p, m.j), m.p);
 }
 
+// Split-twiddle factors held in the pad words of an LDS row tile (four pad words
+// after every 32 words of a row, never touched by the tile exchange): factor e of
+// a row sits in pad block e / kPadTw, kPadTw factors per block.
+constexpr int kTwRatio(int pol) { return pol == kPolicyMont ? 1 : 2; }  // words per table entry
+template <int Pol>
+__device__ __forceinline__ int pad_slot(int e) {
+  constexpr int r = kTwRatio(Pol), per = 4 / r;
+  return (e / per) * (36 / r) + 32 / r + e % per;
+}
+
+// The middle of a fused polynomial-product row (or whole) pass, run on the words
+// of the forward transform's low round while they are still in registers: the
+// pointwise product with the partner transform A's words at the same positions
+// (read from memory, fully reduced), then the inverse transform's low-round
+// stages (DIT, compile-time twiddles of the inverse table), so that the words can
+// go back to the same thread-private places of the LDS tile.
+template <int Pol, int N_LOG, int K>
+struct FusedMid {
+  static constexpr bool kOn = true;
+  const HNTT_GLOBAL T *a_sub;                     // A's words of this sub-transform
+  const HNTT_GLOBAL TwT<Pol> *__restrict__ twg_i;  // inverse per-stage table
+  Mod m;
+  T r2;
+  __device__ __forceinline__ void operator()(T (&v)[1 << K], int base) const {
+    constexpr int M = 1 << K;
+    if constexpr (M >= kVec) {
+      Vec16 q[M / kVec];
+#pragma unroll
+      for (int e = 0; e < M; e += kVec) q[e / kVec] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(a_sub + base + e);
+#pragma unroll
+      for (int e = 0; e < M; e += kVec) {
+        const T *w = reinterpret_cast<const T *>(&q[e / kVec]);
+#pragma unroll
+        for (int i = 0; i < kVec; ++i) v[e + i] = pmul_word(v[e + i], w[i], m, r2);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < M; ++e) v[e] = pmul_word(v[e], a_sub[base + e], m, r2);
+    }
+    round_stages<Pol, N_LOG, K, true, true>(v, 0, base, nullptr, twg_i, m, NoFold{});
+  }
+};
+
 // What happens to a word on its way in from HBM and out to HBM.  The split
-// twiddle of a two-pass transform is applied where the data enters the second
-// pass: on load in the row pass (forward: omega^(s pos) for row s's position
-// pos) and on load in the column pass (inverse: L^-1 conj(omega)^(col rev(pos))).
-// It is the product of two factors, one indexed by the low SIGMA bits of the
-// position and one by the remaining high bits, read from a per-sub-transform
-// table [low factors (2^SIGMA pairs) | high factors (2^(n-SIGMA) pairs)] that is
-// small enough to stay in the L1/L2 caches.  SIGMA is the bit boundary of the
-// pass's first register round, so one factor is fixed per thread group and the
-// other is shared by all lanes of a sub-transform.  TT = false: no split twiddle.
+// twiddle of a two-pass transform (the factor omega^(s pos) between the column
+// and the row transforms of an R x C view, s the bit-reversed row index) is
+// applied in the row pass, for both directions: forward, to row s's
+// word at position pos as it is loaded (before the row transform); inverse, as
+// it is stored (after the row transform, with the conjugate root and L^-1).  It
+// is the product of two factors, one indexed by the low SIGMA bits of the
+// position and one by the remaining high bits, from a per-row table
+// [low factors (2^SIGMA) | high factors (2^(n-SIGMA)) | folded low factors (2^SIGMA)].
+// SIGMA is the bit boundary of the row pass's high register round, so the low
+// factor is fixed per thread in that round and the high factor is shared by all
+// lanes of a row.  TT = false: no split twiddle.
+// LO = false: the low factor is not applied here but folded into the high round's
+// stage next to the split twiddle (see Fold).  HI_LDS: the high factors of the
+// thread's row come from the pads of its LDS tile (hi_lds), staged with the
+// per-stage twiddle table, instead of from the table in memory.
 // Out fixes what out() does: kOutRaw passes words through (the first pass of a
 // two-pass transform), kOutNorm reduces them to [0,p), kOutCond reduces them
 // with p replaced by 0 when normalisation is off (the same instructions either
@@ -318,50 +475,65 @@ __device__ __forceinline__ T pmul_word(T a, T b, const Mod &m, T r2) {
 // with one uniform branch: with the flags tested per word, the compiler computes
 // the reduction for every word and selects afterwards, also when it is not wanted.
 constexpr int kOutRaw = 0, kOutNorm = 1, kOutAny = 2, kOutCond = 3;
-template <int Pol, bool Cols, bool TT, int N_LOG, int SIGMA, int Out = kOutAny>
+template <int Pol, bool Cols, bool TT, int N_LOG, int SIGMA, int Out = kOutAny, bool LO = true, bool HI_LDS = false,
+          bool INV = kInverse>
 struct Edge {
+  static constexpr bool kInv = INV;
   Mod m;
   int normalize, scale;
   T sw, swp;
   __amdgpu_buffer_rsrc_t tt;  // factor tables of the pass
-  uint32_t tt_off;            // byte offset of this sub-transform's first factor
-  uint32_t tt_step;           // bytes between consecutive factors of one sub-transform
-  // pos = lp + up with disjoint bits: lp varies per lane, up is uniform
-  __device__ __forceinline__ T in(T x, int lp, int up) const {
-    if constexpr (TT) {
-      constexpr int kMask = (1 << SIGMA) - 1;
-      const TwT<Pol> hi = buf_load_tw<Pol>(tt, tt_off + (uint32_t)((1 << SIGMA) + (lp >> SIGMA)) * tt_step,
-                                           (uint32_t)(up >> SIGMA) * tt_step);
-      const TwT<Pol> lo = buf_load_tw<Pol>(tt, tt_off + (uint32_t)(lp & kMask) * tt_step,
-                                           (uint32_t)(up & kMask) * tt_step);
-      x = mul_const<Pol>(x, hi, m);  // any input < beta -> [0,2p)
-      x = mul_const<Pol>(x, lo, m);
-      if constexpr (Pol == kPolicyPlain) x = csub<T>(x, m.p);
+  uint32_t tt_off;            // byte offset of this row's first factor
+  const TwT<Pol> *hi_lds;     // HI_LDS: this row's tile base in LDS (table-entry units)
+  // the split twiddle of position pos = lp + up (disjoint bits: lp varies per lane,
+  // up is uniform), times x; any x below beta, result in [0,2p) ([0,p): plain)
+  __device__ __forceinline__ T twist(T x, int lp, int up) const {
+    constexpr uint32_t kTw = sizeof(TwT<Pol>);
+    constexpr int kMask = (1 << SIGMA) - 1;
+    TwT<Pol> hi;
+    if constexpr (HI_LDS) hi = hi_lds[pad_slot<Pol>((lp >> SIGMA) + (up >> SIGMA))];
+    else hi = buf_load_tw<Pol>(tt, tt_off + (uint32_t)((1 << SIGMA) + (lp >> SIGMA)) * kTw, (uint32_t)(up >> SIGMA) * kTw);
+    x = mul_const<Pol, INV>(x, hi, m);
+    if constexpr (LO) {
+      const TwT<Pol> lo = buf_load_tw<Pol>(tt, tt_off + (uint32_t)(lp & kMask) * kTw, (uint32_t)(up & kMask) * kTw);
+      x = mul_const<Pol, INV>(x, lo, m);
     }
+    if constexpr (Pol == kPolicyPlain) x = csub<T>(x, m.p);
+    return x;
+  }
+  __device__ __forceinline__ T in(T x, int lp, int up) const {
+    if constexpr (TT && !INV) x = twist(x, lp, up);
     return x;
   }
   __device__ __forceinline__ T in(T x, int pos) const { return in(x, pos, 0); }
   template <int O>
-  __device__ __forceinline__ Edge<Pol, Cols, TT, N_LOG, SIGMA, O> with_out() const {
-    return {m, normalize, scale, sw, swp, tt, tt_off, tt_step};
+  __device__ __forceinline__ Edge<Pol, Cols, TT, N_LOG, SIGMA, O, LO, HI_LDS, INV> with_out() const {
+    return {m, normalize, scale, sw, swp, tt, tt_off, hi_lds};
   }
-  __device__ __forceinline__ T out(T x, int pos) const {
+  // pos = lp + up as in twist(); the split twiddle of an inverse row pass, then the
+  // output reduction
+  __device__ __forceinline__ T out(T x, int lp, int up) const {
+    if constexpr (TT && INV) x = twist(x, lp, up);
+    return reduce_out(x);
+  }
+  __device__ __forceinline__ T out(T x, int pos) const { return out(x, pos, 0); }
+  __device__ __forceinline__ T reduce_out(T x) const {
     if constexpr (Out == kOutRaw) {
       return x;
     } else if constexpr (Out == kOutNorm) {
-      return reduce_final<Pol>(x, m.p);
+      return reduce_final<Pol, INV>(x, m.p);
     } else if constexpr (Out == kOutCond) {
-      return reduce_final<Pol>(x, normalize ? m.p : (T)0);
-    } else if constexpr (!Cols && kInverse) {
+      return reduce_final<Pol, INV>(x, normalize ? m.p : (T)0);
+    } else if constexpr (!Cols && INV) {
       if (scale) {  // whole inverse transform: times L^-1, then reduced
         if constexpr (Pol == kPolicyMont) x = mont_lazy<Wd>(x, sw, m.p, m.j);
-        else x = shoup_lazy<Wd>(x, sw, swp, m.p);
+        else x = shoup_lazy_sub<Wd>(x, sw, swp, m.p);
         if (normalize) x = csub<T>(x, m.p);
       } else if (normalize) {
-        x = reduce_final<Pol>(x, m.p);
+        x = reduce_final<Pol, INV>(x, m.p);
       }
     } else {
-      if (normalize) x = reduce_final<Pol>(x, m.p);
+      if (normalize) x = reduce_final<Pol, INV>(x, m.p);
     }
     return x;
   }
@@ -394,18 +566,18 @@ struct GlobalIO {
     g.edge = edge.template with_out<O>();
     return g;
   }
-  __device__ __forceinline__ T load2(int lp, int up) const {
+  __device__ __forceinline__ T load_raw(int lp, int up) const {
     if constexpr (Cols) {
-      const T x = buf_load(rsrc, (off + (uint32_t)lp * stride) * (uint32_t)sizeof(T),
-                           (uint32_t)up * stride * (uint32_t)sizeof(T));
-      return edge.in(x, lp, up);
+      return buf_load(rsrc, (off + (uint32_t)lp * stride) * (uint32_t)sizeof(T),
+                      (uint32_t)up * stride * (uint32_t)sizeof(T));
     } else {
-      return edge.in(base[off + (uint32_t)(lp + up)], lp, up);
+      return base[off + (uint32_t)(lp + up)];
     }
   }
+  __device__ __forceinline__ T load2(int lp, int up) const { return edge.in(load_raw(lp, up), lp, up); }
   __device__ __forceinline__ void store2(int lp, int up, T x) const {
-    x = edge.out(x, lp + up);
-    if constexpr (!Cols && !kInverse) {  // (the fused product ends forward transforms only)
+    x = edge.out(x, lp, up);
+    if constexpr (!Cols && !EdgeT::kInv) {  // (the fused product ends forward transforms only)
       if (pm) {
         HNTT_GLOBAL T *q = pm + off + (uint32_t)(lp + up);
         *q = pmul_word(x, *q, edge.m, r2);
@@ -431,7 +603,7 @@ struct GlobalIO {
     T *w = reinterpret_cast<T *>(&q);
 #pragma unroll
     for (int i = 0; i < kVec; ++i) w[i] = edge.out(v[i], pos + i);
-    if (!kInverse && pm) {
+    if (!EdgeT::kInv && pm) {
       HNTT_GLOBAL Vec16 *dst = reinterpret_cast<HNTT_GLOBAL Vec16 *>(pm + (off + (uint32_t)pos));
       const Vec16 pa = *dst;
       const T *pw = reinterpret_cast<const T *>(&pa);
@@ -489,6 +661,16 @@ struct LdsEdgeIO {
   }
 };
 
+// A global source read raw, its input edge applied after the round's hook (DefersIn).
+template <class IO>
+struct DeferredIn {
+  static constexpr bool kContig = IO::kContig;
+  static constexpr bool kDeferIn = true;
+  IO io;
+  __device__ __forceinline__ T load_raw(int lp, int up) const { return io.load_raw(lp, up); }
+  __device__ __forceinline__ T finish(T x, int lp, int up) const { return io.edge.in(x, lp, up); }
+};
+
 // Copy of the N-entry heap twiddle table into LDS, in two steps so that its global
 // loads are in flight together with the tile's: load() issues up to kR loads per
 // thread into registers, store() writes them to LDS (and copies any remainder).
@@ -517,17 +699,56 @@ struct TwStage {
   }
 };
 
+// The 16-byte chunk of a row that copy-in or copy-out slot q moves.  A row tile in LDS has
+// four pad words after every 32 words, so 16 consecutive chunks span 17 or 18
+// 16-byte units and two of them meet in one bank when a 16-lane group of a
+// 16-byte read covers 256 bytes of banks.  Slots are therefore dealt in groups
+// of 16 whose first eight take one 32-word block (8 chunks) and whose last eight
+// the block eight blocks later (8 x 36 words on, i.e. half the banks across):
+// each 16-lane group reads 64 distinct banks, and each eight lanes still store
+// 128 contiguous bytes.  32-bit words only: with 64-bit words 16 consecutive
+// chunks already fall in distinct banks.
+template <int kChunks>
+__device__ __forceinline__ int copyout_chunk(int q) {
+  if constexpr (kVec == 4 && kChunks >= 128) {
+    const int l = q & 15, pr = q >> 4;
+    const int blk = (pr & 7) + ((pr >> 3) << 4) + ((l >> 3) << 3);
+    return (blk << 3) | (l & 7);
+  } else {
+    return q;
+  }
+}
+
 // Padded LDS words per sub-transform (rows: row pitch; cols: rows of the tile).
 template <bool Cols>
 constexpr int padded_len(int N) {
   return Cols ? N + N / 32 : (int)row_padded_len((size_t)N);
 }
 
-template <int Pol, bool Cols, int KH, int KM, int KL, bool TT>
-__global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
+// Waves per SIMD that a pass's LDS tile allows, given to the compiler so that it
+// schedules for that occupancy instead of squeezing registers for more waves
+// than the LDS can host (a 2^5-word-per-thread tile of 32-bit words, or 2^4 of
+// 64-bit words, takes about 144 bytes of LDS per thread: four waves per SIMD).
+// Other passes (no tile, or a tile that leaves room for more waves than their
+// registers do): the default range.
+constexpr bool pass_big_tile(int kh, int km, int kl) {
+  const int kmax = kh > kl ? (kh > km ? kh : km) : (kl > km ? kl : km);
+  return kh > 0 && (1 << kmax) * (int)sizeof(T) >= 128;
+}
+constexpr int pass_waves_min(int kh, int km, int kl) { return pass_big_tile(kh, km, kl) ? 4 : 1; }
+constexpr int pass_waves_max(int kh, int km, int kl) { return pass_big_tile(kh, km, kl) ? 4 : 8; }
+
+// FUSE (32-bit forward row or whole passes of a polynomial product): after the
+// forward transform of B_k's sub-transform, multiply by A_k's words (A_k starts
+// pm_off words earlier), run the inverse transform of the same sub-transform on
+// the product and write it over A_k (see FusedMid).
+template <int Pol, bool Cols, int KH, int KM, int KL, bool TT, bool FUSE = false>
+__global__ void __launch_bounds__(kMaxPassThreads)
+    __attribute__((amdgpu_waves_per_eu(pass_waves_min(KH, KM, KL), pass_waves_max(KH, KM, KL))))
+    k_pass(KernelArgs a) {
   constexpr int N_LOG = KH + KM + KL;
-  // bit boundary of the first register round (split-twiddle factorisation)
-  constexpr int SIGMA = kInverse ? KL : (KM + KL);
+  // bit boundary of the high register round (split-twiddle factorisation of a row pass)
+  constexpr int SIGMA = KM + KL;
   constexpr int N = 1 << N_LOG;
   constexpr int KMAX = KH > KL ? (KH > KM ? KH : KM) : (KL > KM ? KL : KM);
   constexpr int TPT = 1 << (N_LOG - KMAX);
@@ -587,14 +808,26 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
     const HNTT_GLOBAL TwT<Pol> *__restrict__ twg = (const HNTT_GLOBAL TwT<Pol> *)(sp.tw);
 
     HNTT_GLOBAL T *const gbase = (HNTT_GLOBAL T *)(uniform64(ptr));
-    using EdgeT = Edge<Pol, Cols, TT, N_LOG, SIGMA>;
-    EdgeT edge{m, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, make_rsrc(sp.tt, 0), 0, 0};
+    // Row passes with a high register round fold the split twiddle's low factor into
+    // that round (Fold) and, where the row tile's pads hold them, read the high
+    // factors from LDS.
+    constexpr bool kFold = TT && !Cols && KH > 0 && (kInverse || kFwdFold);
+    // The rows of one wave read the same factor index at once; their pads would sit
+    // in the same bank (the row pitch is a multiple of 64 words), so row g's factors
+    // start (g mod rows-per-wave) pad blocks later: 36 words, i.e. another bank.
+    constexpr int kRowsPerWave = TPT >= 64 ? 1 : 64 / TPT;
+    constexpr int kPadTw = 4 / kTwRatio(Pol);  // factors per pad block
+    constexpr bool kHiLds = TT && !Cols && KH > 0 && (kInverse || kFwdHiLds) &&
+                            (1 << KH) + (kRowsPerWave - 1) * kPadTw <= (N / 32) * kPadTw;
+    using EdgeT = Edge<Pol, Cols, TT, N_LOG, SIGMA, kOutAny, !kFold, kHiLds>;
+    constexpr int kPitchT = padded_len<Cols>(N);
+    EdgeT edge{m, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, make_rsrc(sp.tt, 0), 0, nullptr};
     GlobalIO<Cols, EdgeT> gio;
     constexpr uint32_t kTw = sizeof(TwT<Pol>);
-    constexpr uint32_t kTTStride = (1u << SIGMA) + (1u << (N_LOG - SIGMA));
-    const uint32_t nsub = Cols ? (uint32_t)C : (1u << a.log_other);  // sub-transforms per transform
+    // factors per row: low, high, folded low
+    constexpr uint32_t kTTStride = 2u * (1u << SIGMA) + (1u << (N_LOG - SIGMA));
     if constexpr (TT)
-      edge.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt), nsub * kTTStride * kTw);
+      edge.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt), (1u << a.log_other) * kTTStride * kTw);
     gio.base = gbase;
     gio.pm = a.pm_off ? gbase - a.pm_off : nullptr;
     gio.r2 = (T)sp.r2;
@@ -603,20 +836,103 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
       gio.rsrc = make_rsrc((const void *)gbase, (uint32_t)(C * N * sizeof(T)));
       gio.off = col;
       gio.stride = (uint32_t)C;
-      // factor-major table [factor][column]: adjacent columns' factors are adjacent
-      edge.tt_off = col * kTw;
-      edge.tt_step = (uint32_t)C * kTw;
     } else {
       const uint32_t row = (uint32_t)unit * G + g;
       gio.off = row * N;
       gio.stride = 1;
-      // row-major table [row][factor]: a row's lanes read consecutive low factors
       edge.tt_off = row * kTTStride * kTw;
-      edge.tt_step = kTw;
+      if constexpr (kHiLds)
+        edge.hi_lds = reinterpret_cast<const TwT<Pol> *>(tile + g * kPitchT) + (g % kRowsPerWave) * (36 / kTwRatio(Pol));
     }
     gio.edge = edge;
+    // the thread's low factor A and A W for the stage that pairs bit SIGMA (its
+    // twiddle W is the same for all of the thread's butterflies in that stage)
+    using FoldT = std::conditional_t<kFold, Fold<Pol>, NoFold>;
+    FoldT fold{};
+    if constexpr (kFold) {
+      const uint32_t lo = (uint32_t)t & ((1u << SIGMA) - 1);
+      fold.a = buf_load_tw<Pol>(edge.tt, edge.tt_off + lo * kTw, 0);
+      fold.aw = buf_load_tw<Pol>(edge.tt, edge.tt_off + ((1u << SIGMA) + (1u << (N_LOG - SIGMA)) + lo) * kTw, 0);
+    }
+    // High factors of the workgroup's G rows into the pads of their LDS rows: loaded
+    // with the per-stage twiddle table, written with it before the same barrier.
+    constexpr int kHiPer = kHiLds ? ((KH + KMAX - N_LOG) > 0 ? 1 << (KH + KMAX - N_LOG) : 1) : 1;
+    TwT<Pol> hreg[kHiPer];
+    const auto hi_load_from = [&](__amdgpu_buffer_rsrc_t tbl) {
+      if constexpr (kHiLds) {
+        const int nthr = G * TPT;
+#pragma unroll
+        for (int j = 0; j < kHiPer; ++j) {
+          const int i = threadIdx.x + j * nthr;
+          if (i < (G << KH)) {
+            const uint32_t row = (uint32_t)unit * G + (uint32_t)(i >> KH);
+            hreg[j] = buf_load_tw<Pol>(tbl, (row * kTTStride + (1u << SIGMA) + (uint32_t)(i & ((1 << KH) - 1))) * kTw, 0);
+          }
+        }
+      }
+    };
+    const auto hi_load = [&]() { hi_load_from(edge.tt); };
+    // Fused polynomial product (FUSE): the inverse side of the same sub-transform,
+    // written over the partner A_k.  Its split twiddle (rows) is folded and its high
+    // factors come from the row pads exactly as the forward ones.
+    constexpr bool kFoldI = FUSE && TT && KH > 0;
+    constexpr bool kHiLdsI = FUSE && kHiLds;
+    static_assert(kFoldI || !kHiLdsI, "LDS high factors go with the fold");
+    using EdgeI = Edge<Pol, false, TT, N_LOG, SIGMA, kOutAny, !kFoldI, kHiLdsI, true>;
+    const HNTT_GLOBAL TwT<Pol> *__restrict__ twg_i = (const HNTT_GLOBAL TwT<Pol> *)(sp.tw2);
+    EdgeI edge_i{m, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, make_rsrc(sp.tt2, 0), 0, nullptr};
+    GlobalIO<false, EdgeI> gio_a;
+    using FoldI = std::conditional_t<kFoldI, Fold<Pol>, NoFold>;
+    FoldI fold_i{};
+    FusedMid<Pol, N_LOG, KL> fmid{};
+    if constexpr (FUSE) {
+      static_assert(!Cols && !kInverse && sizeof(T) == 4 && Pol != kPolicyMont,
+                    "the fused product runs on 32-bit forward row or whole passes (Shoup policies)");
+      const uint32_t row = (uint32_t)unit * G + g;
+      if constexpr (TT)
+        edge_i.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt2), (1u << a.log_other) * kTTStride * kTw);
+      edge_i.tt_off = row * kTTStride * kTw;
+      if constexpr (kHiLdsI)
+        edge_i.hi_lds = reinterpret_cast<const TwT<Pol> *>(tile + g * kPitchT) + (g % kRowsPerWave) * (36 / kTwRatio(Pol));
+      HNTT_GLOBAL T *const abase = gbase - a.pm_off;
+      gio_a.base = abase;
+      gio_a.pm = nullptr;
+      gio_a.r2 = (T)sp.r2;
+      gio_a.off = row * N;
+      gio_a.stride = 1;
+      gio_a.edge = edge_i;
+      if constexpr (kFoldI) {
+        const uint32_t lo = (uint32_t)t & ((1u << SIGMA) - 1);
+        fold_i.a = buf_load_tw<Pol>(edge_i.tt, edge_i.tt_off + lo * kTw, 0);
+        fold_i.aw = buf_load_tw<Pol>(edge_i.tt, edge_i.tt_off + ((1u << SIGMA) + (1u << (N_LOG - SIGMA)) + lo) * kTw, 0);
+      }
+      fmid = FusedMid<Pol, N_LOG, KL>{abase + (size_t)row * N, twg_i, m, (T)sp.r2};
+    }
+    const auto hi_store = [&]() {
+      if constexpr (kHiLds) {
+        const int nthr = G * TPT;
+        TwT<Pol> *const tile_tw = reinterpret_cast<TwT<Pol> *>(tile);
+#pragma unroll
+        for (int j = 0; j < kHiPer; ++j) {
+          const int i = threadIdx.x + j * nthr;
+          if (i < (G << KH)) {
+            const int gg = i >> KH;
+            tile_tw[gg * (kPitchT / kTwRatio(Pol)) + (gg % kRowsPerWave) * (36 / kTwRatio(Pol)) +
+                    pad_slot<Pol>(i & ((1 << KH) - 1))] = hreg[j];
+          }
+        }
+      }
+    };
 
-    if constexpr (KH == 0) {
+    if constexpr (KH == 0 && FUSE) {
+      // one round: B_k's words, forward stages, times A_k's words, inverse stages, into A_k
+      if (a.zero_upper)
+        round_k<Pol, N_LOG, KL, true, true, decltype(gio), decltype(gio_a), NoHook, NoFold, false>(
+            0, t, TPT, nullptr, twg, m, gio, gio_a, NoHook{}, NoFold{}, fmid);
+      else
+        round_k<Pol, N_LOG, KL, true, false, decltype(gio), decltype(gio_a), NoHook, NoFold, false>(
+            0, t, TPT, nullptr, twg, m, gio, gio_a, NoHook{}, NoFold{}, fmid);
+    } else if constexpr (KH == 0) {
       // one round, HBM to HBM
       if (!kInverse && a.zero_upper) round_k<Pol, N_LOG, KL, true, true>(0, t, TPT, nullptr, twg, m, gio, gio);
       else round_k<Pol, N_LOG, KL, true>(0, t, TPT, nullptr, twg, m, gio, gio);
@@ -627,6 +943,7 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
       TwStage<Pol, N> stage;
       stage.nthr = nthr;
       stage.load(twg);
+      hi_load();
       const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
       if constexpr (!kInverse) {
         // Rows with fewer than 32 threads per row: a high-round load instruction would
@@ -646,32 +963,44 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
             constexpr bool ZU = decltype(zu_tag)::value;
             constexpr int kCh = ZU ? kChunks / 2 : kChunks;  // chunks read per row
             constexpr int kLoad = ZU ? kPer / 2 : kPer;
+            // each thread moves chunks t + j TPT of its own row g
             Vec16 q[kLoad];
 #pragma unroll
-            for (int j = 0; j < kLoad; ++j) {
-              const int i = threadIdx.x + j * nthr;
-              q[j] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(rows0 + (size_t)(i / kCh) * N + (i % kCh) * kVec);
-            }
+            for (int j = 0; j < kLoad; ++j)
+              q[j] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(rows0 + (size_t)g * N +
+                                                                   copyout_chunk<kCh>(t + j * TPT) * kVec);
 #pragma unroll
             for (int j = 0; j < kLoad; ++j) {
-              const int i = threadIdx.x + j * nthr;
-              const int row = i / kCh, c = (i % kCh) * kVec;
-              *reinterpret_cast<Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2)) = q[j];
+              const int c = copyout_chunk<kCh>(t + j * TPT) * kVec;
+              *reinterpret_cast<Vec16 *>(tile + g * kPitch + c + ((c >> 5) << 2)) = q[j];
             }
             stage.store(tws, twg);
-            __syncthreads();  // tile and twiddle table staged
+            hi_store();
+            __syncthreads();  // tile, twiddle table and high factors staged
             const LdsEdgeIO<EdgeT> lin{lio, edge};
-            round_k<Pol, N_LOG, KH, false, ZU>(KM + KL, t, TPT, tws, twg, m, lin, lio);
+            round_k<Pol, N_LOG, KH, false, ZU>(KM + KL, t, TPT, tws, twg, m, lin, lio, NoHook{}, fold);
           };
           if (a.zero_upper) copy_in(std::true_type{});
           else copy_in(std::false_type{});
+        } else if constexpr (TT && kHiLds) {
+          // the row's words are loaded raw, the twiddle table and high factors are
+          // staged meanwhile, and the split twiddle is applied after the barrier
+          const auto staged = [&]() {
+            stage.store(tws, twg);
+            hi_store();
+            __syncthreads();  // twiddle table and high factors staged
+          };
+          const DeferredIn<decltype(gio)> din{gio};
+          if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, din, lio, staged, fold);
+          else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, din, lio, staged, fold);
         } else if constexpr (TT) {
           // the split twiddle's products follow the loads and would all have to
           // finish before a barrier placed after them: the table goes first
           stage.store(tws, twg);
-          __syncthreads();  // twiddle table staged
-          if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio);
-          else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio);
+          hi_store();
+          __syncthreads();  // twiddle table and high factors staged
+          if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio, NoHook{}, fold);
+          else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio, NoHook{}, fold);
         } else {
           const auto staged = [&]() {
             stage.store(tws, twg);
@@ -685,7 +1014,28 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
         }
-        if constexpr (Cols) {
+        if constexpr (FUSE) {
+          // The low round's words stay thread-private from the forward stages through
+          // the product and the inverse low round, so they go back to their own tile
+          // places with no barrier; the inverse table and high factors replace the
+          // forward ones (read only before the barrier above) meanwhile.
+          TwStage<Pol, N> stage_i;
+          stage_i.nthr = nthr;
+          stage_i.load(twg_i);
+          hi_load_from(edge_i.tt);
+          round_k<Pol, N_LOG, KL, true, false, LdsIO<false>, LdsIO<false>, NoHook, NoFold, false>(
+              0, t, TPT, tws, twg, m, lio, lio, NoHook{}, NoFold{}, fmid);
+          stage_i.store(tws, twg_i);
+          hi_store();
+          __syncthreads();  // product tile, inverse table and inverse high factors complete
+          if constexpr (KM > 0) {
+            round_k<Pol, N_LOG, KM, false, false, LdsIO<false>, LdsIO<false>, NoHook, NoFold, true>(
+                KL, t, TPT, tws, twg_i, m, lio, lio);
+            __syncthreads();
+          }
+          round_k<Pol, N_LOG, KH, false, false, LdsIO<false>, decltype(gio_a), NoHook, decltype(fold_i), true>(
+              KM + KL, t, TPT, tws, twg_i, m, lio, gio_a, NoHook{}, fold_i);
+        } else if constexpr (Cols) {
           // the forward column pass is always the first of two: its output is never
           // reduced (the launcher rejects the flag)
           round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, gio.template with_out<kOutRaw>());
@@ -695,20 +1045,20 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           // and write the tile out with consecutive lanes on consecutive 16 bytes.
           round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
-          // (every thread moves kPer vectors; the partner words of the fused product
-          // are all requested before the first is used)
+          // (every thread moves kPer vectors of its row; the partner words of the fused
+          // product are all requested before the first is used)
           constexpr int kPitch = padded_len<false>(N);
           constexpr int kChunks = N / kVec;
           constexpr int kPer = kChunks / TPT;
           static_assert(kPer * TPT == kChunks, "copy-out covers the tile exactly");
           const size_t tile0 = (size_t)unit * G * N;
           const auto ed = edge.template with_out<kOutCond>();
+          // each thread moves chunks t + j TPT of its own row g
           Vec16 o[kPer];
 #pragma unroll
           for (int j = 0; j < kPer; ++j) {
-            const int i = threadIdx.x + j * nthr;
-            const int row = i / kChunks, c = (i % kChunks) * kVec;
-            const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + row * kPitch + c + ((c >> 5) << 2));
+            const int c = copyout_chunk<kChunks>(t + j * TPT) * kVec;
+            const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + g * kPitch + c + ((c >> 5) << 2));
             const T *w = reinterpret_cast<const T *>(&q);
             T *wo = reinterpret_cast<T *>(&o[j]);
 #pragma unroll
@@ -718,11 +1068,9 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
           if (gio.pm) {  // fused pointwise product into the partner transform
             Vec16 pa[kPer];
 #pragma unroll
-            for (int j = 0; j < kPer; ++j) {
-              const int i = threadIdx.x + j * nthr;
-              pa[j] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(out0 + (size_t)(i / kChunks) * N +
-                                                                    (i % kChunks) * kVec);
-            }
+            for (int j = 0; j < kPer; ++j)
+              pa[j] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(out0 + (size_t)g * N +
+                                                                    copyout_chunk<kChunks>(t + j * TPT) * kVec);
 #pragma unroll
             for (int j = 0; j < kPer; ++j) {
               const T *pw = reinterpret_cast<const T *>(&pa[j]);
@@ -732,24 +1080,21 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
             }
           }
 #pragma unroll
-          for (int j = 0; j < kPer; ++j) {
-            const int i = threadIdx.x + j * nthr;
-            *reinterpret_cast<HNTT_GLOBAL Vec16 *>(out0 + (size_t)(i / kChunks) * N + (i % kChunks) * kVec) = o[j];
-          }
+          for (int j = 0; j < kPer; ++j)
+            *reinterpret_cast<HNTT_GLOBAL Vec16 *>(out0 + (size_t)g * N + copyout_chunk<kChunks>(t + j * TPT) * kVec) =
+                o[j];
         }
       } else {
-        // With the split twiddle the table is written first: keeping its registers
-        // live through the round costs the round's loads their overlap.
-        if constexpr (TT) stage.store(tws, twg);
         round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, gio, lio);
-        if constexpr (!TT) stage.store(tws, twg);
-        __syncthreads();  // tile and twiddle table complete
+        stage.store(tws, twg);
+        hi_store();
+        __syncthreads();  // tile, twiddle table and high factors complete
         if constexpr (KM > 0) {
           round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
         }
         const auto last = [&](const auto &dst) {
-          round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, lio, dst);
+          round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, lio, dst, NoHook{}, fold);
         };
         if constexpr (Cols) {
           last(gio.template with_out<kOutCond>());  // column passes never scale
@@ -763,37 +1108,51 @@ __global__ void __launch_bounds__(kMaxPassThreads) k_pass(KernelArgs a) {
   }
 }
 
-template <int Pol, bool Cols, int KH, int KM, int KL, bool TT>
+template <int Pol, bool Cols, int KH, int KM, int KL, bool TT, bool FUSE>
 hipError_t launch_k(const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<Pol, Cols, KH, KM, KL, TT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<Pol, Cols, KH, KM, KL, TT, FUSE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL((k_pass<Pol, Cols, KH, KM, KL, TT>), dim3(blocks), dim3(threads), lds, stream, a);
+  hipLaunchKernelGGL((k_pass<Pol, Cols, KH, KM, KL, TT, FUSE>), dim3(blocks), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 
-// The split twiddle exists only in the second pass of a transform: the inverse
-// column pass and the forward row pass of a split transform.
+// The fused product-and-inverse pass exists for 32-bit forward rows and whole
+// transforms with the Shoup policies (the polynomial product's).
+template <int Pol, bool Cols>
+constexpr bool can_fuse() {
+  return HNTT_WORD == 32 && !kInverse && !Cols && Pol != kPolicyMont;
+}
+
+// The split twiddle exists only in the row pass of a split transform (both directions).
 template <int Pol, bool Cols, int KH, int KM, int KL>
-hipError_t launch_tt(bool tt, const KernelArgs &a, int blocks, int threads, size_t lds, hipStream_t stream) {
-  if constexpr (Cols != kInverse) {
+hipError_t launch_tt(bool tt, bool fuse, const KernelArgs &a, int blocks, int threads, size_t lds,
+                     hipStream_t stream) {
+  if constexpr (can_fuse<Pol, Cols>()) {
+    if (fuse)
+      return tt ? launch_k<Pol, Cols, KH, KM, KL, true, true>(a, blocks, threads, lds, stream)
+                : launch_k<Pol, Cols, KH, KM, KL, false, true>(a, blocks, threads, lds, stream);
+  } else if (fuse) {
+    return hipErrorInvalidValue;
+  }
+  if constexpr (Cols) {
     (void)tt;
-    return launch_k<Pol, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
+    return launch_k<Pol, Cols, KH, KM, KL, false, false>(a, blocks, threads, lds, stream);
   } else {
-    return tt ? launch_k<Pol, Cols, KH, KM, KL, true>(a, blocks, threads, lds, stream)
-              : launch_k<Pol, Cols, KH, KM, KL, false>(a, blocks, threads, lds, stream);
+    return tt ? launch_k<Pol, Cols, KH, KM, KL, true, false>(a, blocks, threads, lds, stream)
+              : launch_k<Pol, Cols, KH, KM, KL, false, false>(a, blocks, threads, lds, stream);
   }
 }
 
 // Round splits per word size; must agree with pass_split().
 template <int Pol, bool Cols>
-hipError_t dispatch_n(int n, bool whole, bool tt, const KernelArgs &a, int blocks, int threads, size_t lds,
+hipError_t dispatch_n(int n, bool whole, bool tt, bool fuse, const KernelArgs &a, int blocks, int threads, size_t lds,
                       hipStream_t s) {
 #define HNTT_CASE(N, KH, KM, KL) \
-  case N: return launch_tt<Pol, Cols, KH, KM, KL>(tt, a, blocks, threads, lds, s);
+  case N: return launch_tt<Pol, Cols, KH, KM, KL>(tt, fuse, a, blocks, threads, lds, s);
 #if HNTT_WORD == 32
   if constexpr (!Cols) {
     if (whole && (n == 9 || n == 10)) {  // one-pass transforms: a full wave each
@@ -869,9 +1228,17 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   a.log_other = log_other;
   a.group = pp.group;
   a.normalize = pp.normalize ? 1 : 0;
-  a.scale = (pp.kind == PassKind::kWhole && pp.inverse) ? 1 : 0;
-  // the fused product belongs to the final forward pass (rows or whole) only
-  if (pp.pm_off && (pp.inverse || pp.kind == PassKind::kCols || !pp.normalize)) return hipErrorInvalidValue;
+  a.scale = (pp.kind == PassKind::kWhole && (pp.inverse || pp.fuse_inverse)) ? 1 : 0;
+  if (pp.fuse_inverse) {
+    // forward row or whole pass of a batch of products; the inverse output it writes
+    // is final (whole: reduced) or the input of the inverse column pass (rows: raw)
+    if (!pp.pm_off || pp.inverse || pp.kind == PassKind::kCols || !pp.table || pp.policy == kPolicyMont ||
+        pp.normalize != (pp.kind == PassKind::kWhole))
+      return hipErrorInvalidValue;
+  } else if (pp.pm_off && (pp.inverse || pp.kind == PassKind::kCols || !pp.normalize)) {
+    // the fused product belongs to the final forward pass (rows or whole) only
+    return hipErrorInvalidValue;
+  }
   if (pp.kind == PassKind::kCols && !pp.inverse && pp.normalize) return hipErrorInvalidValue;
   a.pm_off = pp.pm_off;
   if (pp.zero_upper && (pp.inverse || pp.kind == PassKind::kRows)) return hipErrorInvalidValue;
@@ -879,21 +1246,22 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   if (pp.table) {
     for (int i = 0; i < pp.nslots; ++i) a.slots[i] = pp.slots[i];
   } else {
-    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp, pp.jinv, 0};
+    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp, pp.jinv, 0, nullptr, nullptr};
   }
   const int blocks = (int)total;
   using namespace HNTT_NS;
   const bool tt = pp.table ? pp.slots[0].tt != nullptr : pp.tt != nullptr;
+  const bool fuse = pp.fuse_inverse;
   switch (pp.policy) {
     case kPolicyLazy:
-      return cols ? dispatch_n<kPolicyLazy, true>(n, whole, tt, a, blocks, threads, lds, stream)
-                  : dispatch_n<kPolicyLazy, false>(n, whole, tt, a, blocks, threads, lds, stream);
+      return cols ? dispatch_n<kPolicyLazy, true>(n, whole, tt, fuse, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyLazy, false>(n, whole, tt, fuse, a, blocks, threads, lds, stream);
     case kPolicyPlain:
-      return cols ? dispatch_n<kPolicyPlain, true>(n, whole, tt, a, blocks, threads, lds, stream)
-                  : dispatch_n<kPolicyPlain, false>(n, whole, tt, a, blocks, threads, lds, stream);
+      return cols ? dispatch_n<kPolicyPlain, true>(n, whole, tt, fuse, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyPlain, false>(n, whole, tt, fuse, a, blocks, threads, lds, stream);
     case kPolicyMont:
-      return cols ? dispatch_n<kPolicyMont, true>(n, whole, tt, a, blocks, threads, lds, stream)
-                  : dispatch_n<kPolicyMont, false>(n, whole, tt, a, blocks, threads, lds, stream);
+      return cols ? dispatch_n<kPolicyMont, true>(n, whole, tt, fuse, a, blocks, threads, lds, stream)
+                  : dispatch_n<kPolicyMont, false>(n, whole, tt, fuse, a, blocks, threads, lds, stream);
     default:
       return hipErrorInvalidValue;
   }

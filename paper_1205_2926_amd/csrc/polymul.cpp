@@ -109,6 +109,7 @@ int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_
 
 struct ClassWork {
   int l;
+  Plan plan;  // the class's split and schedule, fixed when the plan is made
   int nfwd, ninv;               // nfwd: entries of each forward table
   const XformEntry *fwd_a, *fwd_b, *inv;  // device tables inside the arena
   const Tables *tab[3];
@@ -135,16 +136,24 @@ struct hntt_polymul_plan {
 
 namespace hntt {
 
+// B_k's last forward pass multiplies into A_k and runs A_k's first inverse pass on
+// the product in the same launch (PassParams::fuse_inverse), saving the product's
+// round trip through memory; when false the product is written and the inverse
+// starts with its own launch.
+constexpr bool kFuseProductInverse = true;
+
 // Enqueue the transforms of a length class listed in a device table.  `which`:
 // 0 = forward of the A_k, 1 = forward of the B_k with the pointwise product fused
-// into their last pass (it multiplies into A_k, which starts L words earlier),
-// 2 = inverse of the A_k.
+// into their last pass (it multiplies into A_k, which starts L words earlier) and,
+// with kFuseProductInverse, A_k's first inverse pass after it, 2 = (the rest of) the
+// inverse of the A_k.
 static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t flags, hipStream_t s) {
-  const Plan plan = effective_plan(ctx, cw.l, 32);
+  const Plan &plan = cw.plan;
   const bool inverse = which == 2;
   const XformEntry *table = which == 0 ? cw.fwd_a : which == 1 ? cw.fwd_b : cw.inv;
   const int count = inverse ? cw.ninv : cw.nfwd;
   const uint32_t pm_off = which == 1 ? (1u << cw.l) : 0u;
+  const bool fuse = which == 1 && kFuseProductInverse;
   if (count == 0) return HNTT_OK;
   PassParams base{};
   base.word_bits = 32;
@@ -163,19 +172,27 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
       sp.jinv = t.jinv;
       sp.r2 = (uint64_t)(((u128)1 << 64) % kPrimes[k]);
       sp.tt = nullptr;
-      // the split twiddle enters with the second pass: rows (forward), columns (inverse)
-      if (which == 0) sp.tw = inverse ? t.inv : t.fwd;               // whole
-      else if (which == 1) {                                          // columns
+      sp.tw2 = sp.tt2 = nullptr;
+      // the split twiddle belongs to the row pass (both directions)
+      if (which == 0) {                                               // whole
         sp.tw = inverse ? t.inv : t.fwd;
-        sp.tt = inverse ? t.tt_inv : nullptr;
+        if (fuse) sp.tw2 = t.inv;
+      } else if (which == 1) {                                        // columns
+        sp.tw = inverse ? t.inv : t.fwd;
+        sp.tt = nullptr;
       } else {                                                        // rows
         sp.tw = inverse ? t.row_inv : t.row_fwd;
-        sp.tt = inverse ? nullptr : t.tt_fwd;
+        sp.tt = inverse ? t.tt_inv : t.tt_fwd;
+        if (fuse) {
+          sp.tw2 = t.row_inv;
+          sp.tt2 = t.tt_inv;
+        }
       }
     }
   };
   hipError_t e;
   if (!plan.split) {
+    if (inverse && kFuseProductInverse) return HNTT_OK;  // done by the fused forward pass of the B_k
     PassParams pp = base;
     pp.kind = PassKind::kWhole;
     pp.n = cw.l;
@@ -183,6 +200,7 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
     pp.group = 1;
     pp.normalize = true;
     pp.pm_off = pm_off;
+    pp.fuse_inverse = fuse;
     pp.zero_upper = !inverse;  // padded operands: the upper half is zero
     slots_for(pp, 0);
     if ((e = launch_traced(ctx, pp, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly whole)");
@@ -200,14 +218,16 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
   rows.group = plan.g_rows;
   slots_for(rows, 2);
   cols.normalize = inverse;
-  rows.normalize = !inverse;
+  rows.normalize = !inverse && !fuse;  // the fused inverse row output feeds the inverse column pass
   rows.pm_off = pm_off;
+  rows.fuse_inverse = fuse;
   cols.zero_upper = !inverse;  // padded operands: rows in the upper half are zero
   if (!inverse) {
     if ((e = launch_traced(ctx, cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
     if ((e = launch_traced(ctx, rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
   } else {
-    if ((e = launch_traced(ctx, rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
+    if (!kFuseProductInverse)
+      if ((e = launch_traced(ctx, rows, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly rows)");
     if ((e = launch_traced(ctx, cols, BatchPtrs{}, s)) != hipSuccess) return hip_err(ctx, e, "launch(poly cols)");
   }
   return HNTT_OK;
@@ -284,12 +304,13 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
     if (!class_count[l]) continue;
     ClassWork cw{};
     cw.l = l;
+    cw.plan = effective_plan(ctx, l, 32);  // the tables below are built for its split
     for (int k = 0; k < 3; ++k) {
       const uint64_t q = kPrimes[k];
       const uint64_t omega = powmod(primitive_root(q), (q - 1) >> l, q);
       if (!no_alloc) {
-        if ((rc = get_tables(ctx, q, omega, l, 32, false, &cw.tab[k]))) return rc;
-      } else if (!(cw.tab[k] = find_tables(ctx, q, omega, l, 32, false))) {
+        if ((rc = get_tables(ctx, q, omega, l, 32, false, cw.plan.c, &cw.tab[k]))) return rc;
+      } else if (!(cw.tab[k] = find_tables(ctx, q, omega, l, 32, false, cw.plan.c))) {
         return perr(ctx, HNTT_EUNSUPPORTED,
                     "twiddle tables of padded length 2^%d are not resident on this context (an earlier "
                     "hntt_polymul_crt or plan with products of that length builds them)", l);

@@ -18,7 +18,8 @@ from typing import Iterable, Sequence
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhntt.so")
+# HNTT_LIB: another build of the library (e.g. one with sanitized host code)
+LIB_PATH = os.environ.get("HNTT_LIB") or os.path.join(_HERE, "libhntt.so")
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5
 PLAIN = 0x1
@@ -55,7 +56,7 @@ class PwDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("log2_len", _c_u32), ("word_bits", _c_u32), ("g_cols", _c_u32), ("g_rows", _c_u32),
-                ("batch_chunk", _c_u32), ("reserved", _c_u32)]
+                ("batch_chunk", _c_u32), ("row_log2", _c_u32)]
 
 
 class PolyDesc(ctypes.Structure):
@@ -381,14 +382,15 @@ class Context:
         return PolymulPlan(self, pairs, outs, plain, graph, workspace, stream, big=True)
 
     # -- schedule tuning ---------------------------------------------------------------------------
-    def set_tuning(self, log2_len: int, word_bits: int, g_cols: int = 0, g_rows: int = 0, batch_chunk: int = 0):
-        t = Tuning(log2_len, word_bits, g_cols, g_rows, batch_chunk, 0)
+    def set_tuning(self, log2_len: int, word_bits: int, g_cols: int = 0, g_rows: int = 0, batch_chunk: int = 0,
+                   row_log2: int = 0):
+        t = Tuning(log2_len, word_bits, g_cols, g_rows, batch_chunk, row_log2)
         self._check(self.lib.hntt_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_plan(self, log2_len: int, word_bits: int) -> dict:
         t = Tuning()
         self._check(self.lib.hntt_get_plan(self.handle, log2_len, word_bits, ctypes.byref(t)))
-        return {k: getattr(t, k) for k in ("g_cols", "g_rows", "batch_chunk")}
+        return {k: getattr(t, k) for k in ("g_cols", "g_rows", "batch_chunk", "row_log2")}
 
     # -- kernel timing -----------------------------------------------------------------------------
     def trace(self, enable: bool = True):

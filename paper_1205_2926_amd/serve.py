@@ -14,10 +14,17 @@ loop on the host:
   buffers the client provides, when it does), frees their memory, and admits
   whatever now fits.
 
+Operands and products travel through a pinned staging buffer unless the
+client brings them in pinned host memory itself (``Request.pinned``): then
+they are copied between its buffers and the device directly, and the host
+moves no data at all.
+
 Twiddle tables stay resident on the context across batches.  A request's
 result never depends on what it was batched with: every product is computed
 independently (checked by the tests: alone vs in the mix, bit for bit).
-Latency is arrival -> result on the host; ``run`` reports p50/p99 and products/s.
+Latency is arrival -> result on the host (stamped after the copy out of
+staging); ``run`` reports p50/p99, products/s, the most batches that were on
+the GPU at once and the fraction of the run during which any batch was.
 """
 from __future__ import annotations
 
@@ -87,12 +94,29 @@ class Request:
     admitted: float = None
     finished: float = None
     batch: int = -1
+    # optional pinned host tensors of the client (int32 operands, int64 product) that a,
+    # b and out are views of: the server then copies straight between them and the device
+    pinned: tuple = None
 
     def __post_init__(self):
         if self.out is not None and not (isinstance(self.out, np.ndarray) and self.out.dtype == np.uint64
                                          and self.out.ndim == 1 and self.out.size >= self.nout
                                          and self.out.flags.c_contiguous and self.out.flags.writeable):
             raise ValueError("out must be a writable contiguous uint64 array of at least na + nb - 1 words")
+        if self.pinned is not None:
+            ta, tb, to = self.pinned
+            ok = all(isinstance(t, torch.Tensor) and t.device.type == "cpu" and t.is_pinned() and t.is_contiguous()
+                     and t.dim() == 1 for t in (ta, tb, to))
+            ok = ok and ta.dtype == tb.dtype == torch.int32 and to.dtype == torch.int64
+            ok = ok and ta.numel() == self.a.size and tb.numel() == self.b.size and to.numel() >= self.nout
+            ok = ok and self.out is not None and np.shares_memory(self.out, to.numpy())
+            if not ok:
+                raise ValueError("pinned must be (a, b, out) pinned contiguous host tensors (int32, int32, int64) "
+                                 "that a, b and out are views of")
+
+    @property
+    def direct(self) -> bool:
+        return self.pinned is not None
 
     @property
     def nout(self) -> int:
@@ -101,6 +125,9 @@ class Request:
     def io_bytes(self) -> int:
         """Operands and product, each 256-byte aligned (the same on the device and in staging)."""
         return _up(4 * self.a.size) + _up(4 * self.b.size) + _up(8 * self.nout)
+
+    def staging_bytes(self) -> int:
+        return 0 if self.direct else self.io_bytes()
 
     def workspace_bound(self) -> int:
         """Upper bound of this product's share of a plan workspace: six padded residue arrays,
@@ -130,6 +157,7 @@ class _Batch:
     stream: torch.cuda.Stream
     event: torch.cuda.Event
     plan: object
+    start: torch.cuda.Event
 
 
 class PolymulServer:
@@ -154,6 +182,9 @@ class PolymulServer:
         self.max_batch = max_batch
         self.plain = plain
         self.inflight: list[_Batch] = []
+        self.max_inflight = 0
+        self.busy_spans: list[tuple[float, float]] = []  # (start, end) ms of each batch on the GPU
+        self.t_ref = None                                  # timing event at the start of run()
         self.nbatches = 0
         self.rejected: list[Request] = []
         # host copies into and out of the staging buffer run on a few threads (numpy
@@ -161,67 +192,95 @@ class PolymulServer:
         self.pool = ThreadPoolExecutor(max_workers=copy_threads)
 
     def _fits_alone(self, r: Request) -> bool:
-        return r.device_bytes() + _GROUP_SLACK <= self.budget and r.io_bytes() <= self.harena.size
+        return r.device_bytes() + _GROUP_SLACK <= self.budget and r.staging_bytes() <= self.harena.size
 
     def _launch(self, reqs, now) -> bool:
-        io = [r.io_bytes() for r in reqs]
-        in_bytes = sum(_up(4 * r.a.size) + _up(4 * r.b.size) for r in reqs)
-        host_bytes = sum(io)
-        dev_bytes = host_bytes + sum(r.workspace_bound() for r in reqs) + _GROUP_SLACK
+        # device layout: staged operands | direct operands | staged products | direct products;
+        # the staging buffer mirrors the staged parts (operands, then products)
+        staged = [r for r in reqs if not r.direct]
+        direct = [r for r in reqs if r.direct]
+        st_in = sum(_up(4 * r.a.size) + _up(4 * r.b.size) for r in staged)
+        st_out = sum(_up(8 * r.nout) for r in staged)
+        all_in = st_in + sum(_up(4 * r.a.size) + _up(4 * r.b.size) for r in direct)
+        io_bytes = sum(r.io_bytes() for r in reqs)
+        dev_bytes = io_bytes + sum(r.workspace_bound() for r in reqs) + _GROUP_SLACK
+        host_bytes = st_in + st_out
         doff = self.arena.alloc(dev_bytes)
         if doff is None:
             return False
-        hoff = self.harena.alloc(host_bytes)
-        if hoff is None:
-            self.arena.release(doff, dev_bytes)
-            return False
+        hoff = 0
+        if host_bytes:
+            hoff = self.harena.alloc(host_bytes)
+            if hoff is None:
+                self.arena.release(doff, dev_bytes)
+                return False
         busy = {id(b.stream) for b in self.inflight}
         stream = next(s for s in self.streams if id(s) not in busy)
-        # layout (same relative offsets on both sides): all operands, then all products
-        pairs, outs, out_offs, copies = [], [], [], []
-        cur, ocur = 0, in_bytes
-        for r in reqs:
+        pairs, outs, out_offs, copies, direct_in = [], [], {}, [], []
+        cur, ocur = 0, all_in
+        for r in staged + direct:
             na, nb = r.a.size, r.b.size
-            copies.append((hoff + cur, r.a))
             da = self.arena_t[doff + cur:doff + cur + 4 * na].view(torch.int32)
+            if r.direct:
+                direct_in.append((da, r.pinned[0]))
+            else:
+                copies.append((hoff + cur, r.a))
             cur += _up(4 * na)
-            copies.append((hoff + cur, r.b))
             db = self.arena_t[doff + cur:doff + cur + 4 * nb].view(torch.int32)
+            if r.direct:
+                direct_in.append((db, r.pinned[1]))
+            else:
+                copies.append((hoff + cur, r.b))
             cur += _up(4 * nb)
             do = self.arena_t[doff + ocur:doff + ocur + 8 * r.nout].view(torch.int64)
             pairs.append((da, db))
             outs.append(do)
-            out_offs.append(ocur)
+            out_offs[id(r)] = ocur - all_in + st_in  # staging offset of a staged product
             ocur += _up(8 * r.nout)
 
         def pack(job):
             off, src = job
             self.host_np[off:off + 4 * src.size].view(np.uint32)[:] = src
 
-        list(self.pool.map(pack, copies))
-        ws = self.arena_t[doff + host_bytes:doff + dev_bytes]
+        if copies:
+            list(self.pool.map(pack, copies))
+        ws = self.arena_t[doff + io_bytes:doff + dev_bytes]
         with torch.cuda.stream(stream):
-            self.arena_t[doff:doff + in_bytes].copy_(self.host_t[hoff:hoff + in_bytes], non_blocking=True)
+            start = torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            if st_in:
+                self.arena_t[doff:doff + st_in].copy_(self.host_t[hoff:hoff + st_in], non_blocking=True)
+            for dst, src in direct_in:
+                dst.copy_(src, non_blocking=True)
             plan = self.ctx.polymul_plan(pairs, outs, plain=self.plain, graph=False, workspace=ws, stream=stream)
             plan.execute(stream=stream)
-            self.host_t[hoff + in_bytes:hoff + host_bytes].copy_(self.arena_t[doff + in_bytes:doff + host_bytes],
-                                                                 non_blocking=True)
-            ev = torch.cuda.Event()
+            if st_out:
+                self.host_t[hoff + st_in:hoff + host_bytes].copy_(self.arena_t[doff + all_in:doff + all_in + st_out],
+                                                                  non_blocking=True)
+            for r, do in zip(staged + direct, outs):
+                if r.direct:
+                    r.pinned[2][:r.nout].copy_(do, non_blocking=True)
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(stream)
-        for r in reqs:
+        order = staged + direct
+        for r in order:
             r.admitted = now
             r.batch = self.nbatches
-        self.inflight.append(_Batch(self.nbatches, reqs, doff, dev_bytes, hoff, host_bytes, out_offs, stream, ev,
-                                    plan))
+        self.inflight.append(_Batch(self.nbatches, order, doff, dev_bytes, hoff, host_bytes,
+                                    [out_offs[id(r)] for r in order], stream, ev, plan, start))
+        self.max_inflight = max(self.max_inflight, len(self.inflight))
         self.nbatches += 1
         return True
 
-    def _retire(self, now) -> int:
+    def _retire(self, t0: float) -> int:
         done = 0
         for bt in list(self.inflight):
             if bt.event.query():
                 def unpack(job, base=bt.host_off):
                     r, o = job
+                    if r.direct:  # already in the client's pinned buffer
+                        r.result = r.out[:r.nout]
+                        return
                     src = self.host_np[base + o:base + o + 8 * r.nout].view(np.uint64)
                     if r.out is not None:  # into the client's buffer: no allocation here
                         np.copyto(r.out[:r.nout], src)
@@ -230,14 +289,30 @@ class PolymulServer:
                         r.result = src.copy()
 
                 list(self.pool.map(unpack, zip(bt.reqs, bt.out_offs)))
+                finished = time.perf_counter() - t0  # the results are on the host now
                 for r in bt.reqs:
-                    r.finished = now
+                    r.finished = finished
+                if self.t_ref is not None:
+                    self.busy_spans.append((self.t_ref.elapsed_time(bt.start), self.t_ref.elapsed_time(bt.event)))
                 bt.plan.destroy()
                 self.arena.release(bt.dev_off, bt.dev_bytes)
-                self.harena.release(bt.host_off, bt.host_bytes)
+                if bt.host_bytes:
+                    self.harena.release(bt.host_off, bt.host_bytes)
                 self.inflight.remove(bt)
                 done += len(bt.reqs)
         return done
+
+    def _busy_ms(self) -> float:
+        """Time during which at least one batch was on the GPU (union of the batches' spans)."""
+        total, end = 0.0, None
+        for a, b in sorted(self.busy_spans):
+            if end is None or a > end:
+                total += b - a
+                end = b
+            elif b > end:
+                total += b - end
+                end = b
+        return total
 
     def run(self, requests: list[Request], time_limit: float = 600.0) -> dict:
         """Serve `requests` (arrival in seconds from now); returns throughput and latency statistics."""
@@ -245,6 +320,8 @@ class PolymulServer:
         pending: deque = deque()
         nxt = 0
         finished = 0
+        self.t_ref = torch.cuda.Event(enable_timing=True)
+        self.t_ref.record(torch.cuda.current_stream())
         t0 = time.perf_counter()
         while finished + len(self.rejected) < len(reqs):
             now = time.perf_counter() - t0
@@ -257,7 +334,7 @@ class PolymulServer:
                 else:
                     pending.append(r)
                 nxt += 1
-            finished += self._retire(now)
+            finished += self._retire(t0)
             # admission: the longest arrival-ordered prefix of the queue that fits now
             while pending and len(self.inflight) < len(self.streams):
                 group, dev, host = [], _GROUP_SLACK, 0
@@ -265,10 +342,10 @@ class PolymulServer:
                 host_free = self.harena.size - self.harena.used
                 while pending and len(group) < self.max_batch:
                     r = pending[0]
-                    if dev + r.device_bytes() > dev_free or host + r.io_bytes() > host_free:
+                    if dev + r.device_bytes() > dev_free or host + r.staging_bytes() > host_free:
                         break
                     dev += r.device_bytes()
-                    host += r.io_bytes()
+                    host += r.staging_bytes()
                     group.append(pending.popleft())
                 if not group or not self._launch(group, now):
                     for r in reversed(group):
@@ -279,6 +356,8 @@ class PolymulServer:
                 if wait > 0:
                     time.sleep(min(wait, 0.001))
         wall = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        busy_ms = self._busy_ms()
         lat = np.array([r.finished - r.arrival for r in reqs if r.result is not None])
         return {
             "requests": len(reqs),
@@ -290,6 +369,8 @@ class PolymulServer:
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
             "mean_ms": float(lat.mean() * 1e3) if lat.size else None,
+            "max_inflight": self.max_inflight,
+            "gpu_busy_frac": busy_ms / (wall * 1e3) if wall > 0 else 0.0,
             "peak_bytes": self.arena.peak,
             "budget_bytes": self.budget,
             "host_staging_bytes": self.harena.size,
@@ -299,7 +380,7 @@ class PolymulServer:
         """Release the device arena and the pinned staging buffer (in-flight batches first)."""
         if self.inflight:
             torch.cuda.synchronize()
-            self._retire(0.0)
+            self._retire(time.perf_counter())
         self.pool.shutdown()
         self.arena_t = None
         self.host_t = None
@@ -307,17 +388,25 @@ class PolymulServer:
 
 
 def make_requests(seed: int, count: int, rate_per_s: float, lo_bits: float = 10, hi_bits: float = 20,
-                  client_out: bool = False):
+                  client_out: bool = False, pinned: bool = False):
     """Poisson arrivals of products with log-uniform lengths (see workloads.poisson_requests).
     client_out: each request carries a result buffer that the client allocated and touched
     beforehand (as a client reusing its buffers would have), so that the server's unpacking
-    is one copy per product and no page faults."""
+    is one copy per product and no page faults.
+    pinned: the client keeps operands and result buffer in pinned host memory (as a client
+    that reuses pinned buffers would), so the server copies straight to and from them."""
     from .workloads import poisson_requests
     reqs = []
     for i, (t, a, b) in enumerate(poisson_requests(seed, count, rate_per_s, lo_bits, hi_bits)):
-        out = None
-        if client_out:
+        out, pin = None, None
+        if pinned:
+            ta = torch.from_numpy(a.view(np.int32)).pin_memory()
+            tb = torch.from_numpy(b.view(np.int32)).pin_memory()
+            to = torch.zeros(a.size + b.size - 1, dtype=torch.int64).pin_memory()
+            a, b, out = ta.numpy().view(np.uint32), tb.numpy().view(np.uint32), to.numpy().view(np.uint64)
+            pin = (ta, tb, to)
+        elif client_out:
             out = np.empty(a.size + b.size - 1, np.uint64)
             out.fill(0)
-        reqs.append(Request(i, t, a, b, out))
+        reqs.append(Request(i, t, a, b, out, pinned=pin))
     return reqs

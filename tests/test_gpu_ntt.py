@@ -369,7 +369,7 @@ def test_pointwise_mul(ctx, orc, wb, p):
 def test_schedule_independence(ctx, orc, wb, l, policy):
     """Every legal schedule gives bit-identical results (a cross-schedule check that would
     expose LDS races or indexing mistakes tied to one tile shape)."""
-    from paper_1205_2926_amd.autotune import candidates
+    from paper_1205_2926_amd.autotune import candidates, splits
     p, g = (P30, G30) if wb == 32 else (P62, G62)
     w = _omega(orc, p, g, l)
     dt = _np_dtype(wb)
@@ -378,8 +378,13 @@ def test_schedule_independence(ctx, orc, wb, l, policy):
     ref = None
     cands = candidates(ctx, l, wb, batch)
     assert len(cands) >= 4
-    for cand in cands[:: max(1, len(cands) // 10)]:
-        ctx.set_tuning(l, wb, cand["g_cols"], cand["g_rows"], cand["batch_chunk"])
+    picks = cands[:: max(1, len(cands) // 10)]
+    # every split of the stages between the passes, whatever the stride above lands on
+    for c in sorted({k["row_log2"] for k in cands}):
+        picks.append(next(k for k in cands if k["row_log2"] == c))
+    assert len({k["row_log2"] for k in picks}) == len(splits(ctx, l, wb)) and (l <= 12 or len(splits(ctx, l, wb)) >= 2)
+    for cand in picks:
+        ctx.set_tuning(l, wb, cand["g_cols"], cand["g_rows"], cand["batch_chunk"], cand["row_log2"])
         t = dev(x)
         ctx.ntt_forward(t, p, w, **_kw(policy))
         got = host(t, dt)
