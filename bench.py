@@ -42,8 +42,8 @@ OPS_BFLY = {"lazy": 9, "plain": 12}
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="transforms (forward + inverse, length 2^20) in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -171,11 +171,17 @@ def measured_counter(kernel: str, field: str = "bytes_per_launch"):
     return rec.get(field, {}).get(kernel)
 
 
+CPU_SHARE_PER_GPU = 16
+
+
 def cpu_baseline(cfg, w, x_np, sample):
     import numpy as np
     import oracle
     orc = oracle.Oracle()
-    cores = min(16, len(os.sched_getaffinity(0)))
+    # one thread per core of this GPU's share of the host: 16 cores per GPU (the share a
+    # one-GPU job may occupy), fewer if the process may run on fewer
+    allowed = len(os.sched_getaffinity(0))
+    cores = min(CPU_SHARE_PER_GPU, allowed)
     l, p = cfg.log2_len, cfg.p
     rows = [x_np[i % x_np.shape[0]].astype(np.uint64) for i in range(sample)]
 
@@ -199,7 +205,9 @@ def cpu_baseline(cfg, w, x_np, sample):
                       f"thread, {cores} threads, {wall:.2f} s wall", "wall_s": wall,
             "single_thread": {"value": 2 * l * (1 << (l - 1)) / single, "unit": "butterflies/s",
                               "sample": "one transform, forward + inverse, on one thread", "wall_s": single},
-            "cpu_model": cpu_model()}, fwd, rows
+            "cpu_model": cpu_model(), "host_cores_total": os.cpu_count(), "host_cores_allowed": allowed,
+            "cores_note": f"{cores} threads: the CPU share of one GPU on this host "
+                          f"({os.cpu_count()} logical cores in total, {allowed} allowed to this process)"}, fwd, rows
 
 
 def cpu_model() -> str:

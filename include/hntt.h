@@ -194,6 +194,13 @@ typedef struct hntt_polymul_plan hntt_polymul_plan;
 int hntt_polymul_plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint32_t flags, void *workspace,
                              size_t workspace_bytes, void *stream, hntt_polymul_plan **out);
 size_t hntt_polymul_plan_workspace_bytes(const hntt_polymul_plan *plan);
+/* How the plan's last execution was enqueued: HNTT_EXEC_NONE (not executed yet),
+ * HNTT_EXEC_GRAPH (one HIP graph launch), HNTT_EXEC_DIRECT (kernel launches, as
+ * asked by HNTT_NO_GRAPH or while tracing is on), or HNTT_EXEC_CAPTURE_FAILED
+ * (kernel launches because recording the graph failed; the plan keeps launching
+ * directly, and msg, when not NULL, receives the reason).  Host only. */
+enum { HNTT_EXEC_NONE = 0, HNTT_EXEC_GRAPH = 1, HNTT_EXEC_DIRECT = 2, HNTT_EXEC_CAPTURE_FAILED = 3 };
+int hntt_polymul_plan_exec_mode(const hntt_polymul_plan *plan, const char **msg);
 /* Workspace a plan for these descriptors needs, computed on the host from the
  * lengths alone (pointers are not read), e.g. for admission control before any
  * device memory is committed.  Errors: EINVAL, EUNSUPPORTED. */

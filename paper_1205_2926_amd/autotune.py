@@ -5,7 +5,7 @@ the GPU under every legal schedule in a small search space (how Algorithm 1's
 stages are split between the column and the row pass, columns per workgroup in
 the column pass, rows per workgroup in the row pass, transforms per chunk) and
 installs the fastest one on the context with ``Context.set_tuning``.  ``tune_polymul`` does the same per length class of a batch of
-exact products, timing the whole batch plan.  The GPU is kept busy for a second before the first
+exact products, timing the whole batch plan, and caches the choice per length-class histogram.  The GPU is kept busy for a second before the first
 trial, and the six fastest candidates are timed again in turn, five times
 each over 20 repetitions, and ranked by their median.  Results are cached in a JSON file keyed by the GPU's compute-unit
 count, memory size and the shape (``$HNTT_TUNE_CACHE``, default ``~/.cache/hntt/tune.json``).  The
@@ -187,8 +187,20 @@ def _plan_ms(plan, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def _poly_key(pairs, plain, big):
+    """Cache key of a product batch: the device, the kind and policy, and how many products
+    fall in each length class (the plan's launches depend on nothing else)."""
+    counts = {}
+    for a, b in pairs:
+        l = max(1, (max(a.numel(), b.numel()) - 1).bit_length() + 1)
+        counts[l] = counts.get(l, 0) + 1
+    hist = ",".join(f"{l}:{counts[l]}" for l in sorted(counts))
+    return _key(0, 32, len(pairs), "plain" if plain else "lazy").replace(
+        "|l=0|", f"|{'bigmul' if big else 'polymul'}|classes={hist}|")
+
+
 def tune_polymul(ctx, pairs, outs, plain: bool = False, reps: int = 3, verbose: bool = False,
-                 big: bool = False) -> dict:
+                 big: bool = False, use_cache: bool = True) -> dict:
     """Pick and install, length class by length class, the split of the stages between the two
     passes and the (columns, rows) per workgroup of the two-pass transforms of a batch of exact
     products (`Context.polymul_plan` arguments, or `Context.bigmul_plan` ones with big=True), by
@@ -199,6 +211,12 @@ def tune_polymul(ctx, pairs, outs, plain: bool = False, reps: int = 3, verbose: 
     have nothing to tune."""
     make = ctx.bigmul_plan if big else ctx.polymul_plan
     classes = sorted({max(1, (max(a.numel(), b.numel()) - 1).bit_length() + 1) for a, b in pairs}, reverse=True)
+    key = _poly_key(pairs, plain, big)
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        for l, v in cache[key]["classes"].items():
+            ctx.set_tuning(int(l), 32, v["g_cols"], v["g_rows"], 0, v["row_log2"])
+        return {**cache[key], "classes": {int(l): v for l, v in cache[key]["classes"].items()}, "cached": True}
     chosen = {}
     t0 = time.time()
     plan = make(pairs, outs, plain=plain)
@@ -240,7 +258,11 @@ def tune_polymul(ctx, pairs, outs, plain: bool = False, reps: int = 3, verbose: 
                      "default": {k: default[k] for k in ("row_log2", "g_cols", "g_rows")}}
         if verbose:
             print(f"  class 2^{l}: {chosen[l]}", flush=True)
-    return {"classes": chosen, "tune_s": time.time() - t0}
+    rec = {"classes": chosen, "tune_s": time.time() - t0}
+    if use_cache:
+        cache[key] = rec
+        save_cache(cache)
+    return rec
 
 
 def main():

@@ -18,6 +18,7 @@ exactly or modulo two 61-bit primes, and numpy's own modular product.
 from __future__ import annotations
 
 import random
+import sys
 import time
 
 import numpy as np
@@ -62,6 +63,43 @@ def _events_ms(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def _policies(args, all_policies):
+    """The butterfly policies to measure: lazy only under --no-plain (which also drops the
+    Montgomery comparison), else all of them."""
+    return all_policies[:1] if args.no_plain else all_policies
+
+
+def _ratios(res, key):
+    return {f"lazy_over_{k}": res[k][key] / res["lazy"][key] for k in res if k != "lazy"}
+
+
+def _time_plan(make_plan, count, args):
+    """Batch time of a product plan over max(3, steps/2) executions after one untimed one, and
+    how they were enqueued: one graph launch, or kernel by kernel (with the reason when
+    recording the graph failed).  A second plan of the same batch without the graph gives the
+    kernel-by-kernel time beside it."""
+    res = {}
+    for graph in (True, False):
+        plan = make_plan(graph)
+        plan.execute()
+        torch.cuda.synchronize()
+        ms = _events_ms(plan.execute, max(3, args.steps // 2))
+        mode = plan.exec_mode
+        plan.destroy()
+        if graph:
+            res = {"ms_per_batch": ms, "products_per_s": count / (ms / 1e3), "executed_as": mode}
+        else:
+            res["direct"] = {"ms_per_batch": ms, "executed_as": mode}
+    return res
+
+
+def _schedules(tuned):
+    if tuned is not None:
+        return {"schedules": {f"2^{l}": {k: v[k] for k in ("row_log2", "g_cols", "g_rows")}
+                              for l, v in tuned["classes"].items()}, "tuned": True}
+    return {"tuned": False}
+
+
 def single1k(args):
     cfg = SINGLE_1K
     ctx = hntt.Context(0)
@@ -97,9 +135,10 @@ def u64(args):
     x_np = cfg.data()
     x = torch.from_numpy(x_np.view(np.int64)).cuda()
     res = {}
-    for policy in ("lazy", "plain", "mont"):
+    for policy in _policies(args, ("lazy", "plain", "mont")):
         kw = {"plain": policy == "plain", "mont": policy == "mont"}
-        autotune.tune(ctx, x, p, w, policy=policy)
+        if not args.no_tune:
+            autotune.tune(ctx, x, p, w, policy=policy)
         # untimed round trips first: a schedule from the tuning cache skips the tuner's trials,
         # which would otherwise have built this policy's tables and warmed the GPU
         autotune.warm(ctx, x, p, w, policy, 0.5)
@@ -110,9 +149,7 @@ def u64(args):
     ctx.close()
     return {"metric": "NTT butterflies/s, 64-bit words", "unit": "butterflies/s",
             "value": res["lazy"]["butterflies_per_s"], "workload": "8 x 2^22 forward+inverse, p=2^62-ish, u64",
-            "p": p, "lazy": res["lazy"], "plain": res["plain"], "mont": res["mont"],
-            "lazy_over_plain": res["plain"]["ms_per_step"] / res["lazy"]["ms_per_step"],
-            "lazy_over_mont": res["mont"]["ms_per_step"] / res["lazy"]["ms_per_step"]}
+            "p": p, **res, **_ratios(res, "ms_per_step")}
 
 
 def polymul(args):
@@ -130,19 +167,14 @@ def polymul(args):
         bfly += 9 * l * (1 << (l - 1))
         words += 1 << l
     res = {}
-    for plain in (False, True):
+    for policy in _policies(args, ("lazy", "plain")):
+        plain = policy == "plain"
         # each policy gets its own per-class schedules, timed on this batch's own plan
-        tuned = autotune.tune_polymul(ctx, dpairs, outs, plain=plain)
-        plan = ctx.polymul_plan(dpairs, outs, plain=plain)
-        plan.execute()
-        torch.cuda.synchronize()
-        ms = _events_ms(plan.execute, max(3, args.steps // 2))
-        res["plain" if plain else "lazy"] = {"ms_per_batch": ms, "products_per_s": len(pairs) / (ms / 1e3),
-                                             "butterflies_per_s": bfly / (ms / 1e3),
-                                             "schedules": {f"2^{l}": {k: v[k] for k in ("row_log2", "g_cols", "g_rows")}
-                                                           for l, v in tuned["classes"].items()},
-                                             "tune_s": tuned["tune_s"]}
-        plan.destroy()
+        tuned = None if args.no_tune else autotune.tune_polymul(ctx, dpairs, outs, plain=plain)
+        res[policy] = _time_plan(lambda graph: ctx.polymul_plan(dpairs, outs, plain=plain, graph=graph),
+                                 len(pairs), args)
+        res[policy]["butterflies_per_s"] = bfly / (res[policy]["ms_per_batch"] / 1e3)
+        res[policy].update(_schedules(tuned))
     rr = random.Random(7)
     for i in rr.sample(range(len(pairs)), 64):
         assert _product_ok(*pairs[i], outs[i].cpu().numpy().view(np.uint64)), "polymul result mismatch"
@@ -150,18 +182,22 @@ def polymul(args):
     return {"metric": "exact polynomial products/s (3 primes + CRT, one graph launch)", "unit": "products/s",
             "value": res["lazy"]["products_per_s"],
             "workload": "4096 pairs, n log-uniform 2^8..2^16, coefficients < 2^20", "sum_padded_len": words,
-            "butterflies_per_batch": bfly, "lazy": res["lazy"], "plain": res["plain"],
-            "lazy_over_plain": res["plain"]["ms_per_batch"] / res["lazy"]["ms_per_batch"]}
+            "butterflies_per_batch": bfly, **res, **_ratios(res, "ms_per_batch")}
 
 
 def serving(args):
-    """Continuous batching of exact products (Poisson arrivals).  Saturation throughput is the
-    highest achieved rate while the offered rate grows by 1.5x steps (from the rate of a burst
-    queued at time 0) until the server falls behind; the offered rate is then swept over
-    fractions of it, reporting achieved products/s and arrival-to-result p50/p99."""
+    """Continuous batching of exact products (Poisson arrivals), for two kinds of client: one
+    that keeps operands and result buffers in pinned host memory (the server copies straight
+    to and from them: the reported value) and one with pageable buffers (through the server's
+    pinned staging).  Saturation throughput is the highest achieved rate while the offered
+    rate grows by 1.5x steps (from the rate of a burst queued at time 0) until the server falls
+    behind; the offered rate is then swept over fractions of it, reporting achieved products/s,
+    arrival-to-result p50/p99, the fraction of the wall time the GPU had a batch running, and
+    the most batches in flight at once."""
     from .serve import PolymulServer, make_requests
     ctx = hntt.Context(0)
     budget = 8 << 30
+    keys = ("offered_rate", "products_per_s", "p50_ms", "p99_ms", "gpu_busy_frac", "max_inflight")
 
     def serve(reqs):
         srv = PolymulServer(ctx, budget)
@@ -170,41 +206,53 @@ def serving(args):
         finally:
             srv.close()
 
-    def at_rate(rate, seed=5):
+    def at_rate(rate, pinned, seed=5):
         count = int(min(800, max(60, rate * 0.5)))
-        reqs = make_requests(seed=seed, count=count, rate_per_s=rate, client_out=True)
+        reqs = make_requests(seed=seed, count=count, rate_per_s=rate, client_out=True, pinned=pinned)
         st = serve(reqs)
         st.update({"offered_rate": rate})
         return st, reqs
 
+    def client(pinned, sweep_fracs):
+        burst = serve(make_requests(seed=5, count=400, rate_per_s=1e9, client_out=True, pinned=pinned))
+        # saturation: raise the offered rate until the server falls behind (achieved < 90% offered)
+        rate, probes = burst["products_per_s"], []
+        for _ in range(10):
+            st, _ = at_rate(rate, pinned)
+            probes.append({k: st[k] for k in keys})
+            print(f"serving {'pinned' if pinned else 'pageable'} probe {probes[-1]}", file=sys.stderr, flush=True)
+            if st["products_per_s"] < 0.9 * rate:
+                break
+            rate *= 1.5
+        mu = max(p["products_per_s"] for p in probes)
+        sweep, reqs = [], []
+        for frac in sweep_fracs:
+            st, reqs = at_rate(frac * mu, pinned)
+            st.update({"offered_fraction": frac})
+            sweep.append(st)
+            print(f"serving {'pinned' if pinned else 'pageable'} at {frac} of saturation: "
+                  f"{ {k: st[k] for k in keys} }", file=sys.stderr, flush=True)
+        # every coefficient of a tenth of the last run's results
+        for r in reqs[:: max(1, len(reqs) // 10)]:
+            assert _product_ok(r.a, r.b, r.result[: r.nout]), "served product mismatch"
+        return {"products_per_s": mu,
+                "burst": {k: burst[k] for k in ("requests", "products_per_s", "p50_ms", "p99_ms", "batches",
+                                                "gpu_busy_frac", "max_inflight")},
+                "saturation_probes": probes,
+                "sweep": [{k: st[k] for k in ("offered_fraction", *keys, "mean_ms", "requests", "batches",
+                                              "peak_bytes")} for st in sweep]}
+
     # warm the twiddle tables of every length class
     serve(make_requests(seed=50, count=40, rate_per_s=1e9))
-    burst = serve(make_requests(seed=5, count=400, rate_per_s=1e9, client_out=True))  # all queued at time 0
-    # saturation: raise the offered rate until the server falls behind (achieved < 90% offered)
-    rate, probes = burst["products_per_s"], []
-    for _ in range(10):
-        st, _ = at_rate(rate)
-        probes.append({k: st[k] for k in ("offered_rate", "products_per_s", "p50_ms", "p99_ms")})
-        if st["products_per_s"] < 0.9 * rate:
-            break
-        rate *= 1.5
-    mu = max(p["products_per_s"] for p in probes)
-    sweep = []
-    for frac in (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
-        st, reqs = at_rate(frac * mu)
-        st.update({"offered_fraction": frac})
-        sweep.append(st)
-    # every coefficient of a tenth of the last run's results
-    for r in reqs[:: max(1, len(reqs) // 10)]:
-        assert _product_ok(r.a, r.b, r.result[: r.nout]), "served product mismatch"
+    pinned = client(True, (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2))
+    staged = client(False, () if args.no_plain else (0.1, 0.5, 1.0))
     ctx.close()
     return {"metric": "serving: products/s at saturation, p50/p99 latency vs offered rate", "unit": "products/s",
-            "value": mu, "workload": "Poisson stream, n log-uniform 2^10..2^20, 3 primes + CRT, budget 8 GiB, "
-                                     "results written into client-provided buffers",
-            "burst": {k: burst[k] for k in ("requests", "products_per_s", "p50_ms", "p99_ms", "batches")},
-            "saturation_probes": probes,
-            "sweep": [{k: st[k] for k in ("offered_fraction", "offered_rate", "products_per_s", "p50_ms", "p99_ms",
-                                          "mean_ms", "requests", "batches", "peak_bytes")} for st in sweep]}
+            "value": pinned["products_per_s"],
+            "workload": "Poisson stream, n log-uniform 2^10..2^20, 3 primes + CRT, budget 8 GiB; value: client "
+                        "buffers in pinned host memory",
+            "pinned_client": pinned, "pageable_client": staged,
+            "pinned_over_pageable": pinned["products_per_s"] / staged["products_per_s"]}
 
 
 def bigmul(args):
@@ -221,16 +269,11 @@ def bigmul(args):
     dpairs = [(torch.from_numpy(a.view(np.int32)).cuda(), torch.from_numpy(b.view(np.int32)).cuda()) for a, b in pairs]
     outs = [torch.empty(2 * n, dtype=torch.int32, device="cuda") for _ in range(count)]
     res = {}
-    for policy in ("lazy", "plain"):
-        tuned = autotune.tune_polymul(ctx, dpairs, outs, plain=policy == "plain", big=True)
-        plan = ctx.bigmul_plan(dpairs, outs, plain=policy == "plain")
-        plan.execute()
-        torch.cuda.synchronize()
-        ms = _events_ms(plan.execute, max(3, args.steps // 2))
-        res[policy] = {"ms_per_batch": ms, "products_per_s": count / (ms / 1e3),
-                       "schedules": {f"2^{l}": {k: v[k] for k in ("row_log2", "g_cols", "g_rows")}
-                                     for l, v in tuned["classes"].items()}}
-        plan.destroy()
+    for policy in _policies(args, ("lazy", "plain")):
+        plain = policy == "plain"
+        tuned = None if args.no_tune else autotune.tune_polymul(ctx, dpairs, outs, plain=plain, big=True)
+        res[policy] = _time_plan(lambda graph: ctx.bigmul_plan(dpairs, outs, plain=plain, graph=graph), count, args)
+        res[policy].update(_schedules(tuned))
     for i in (0, count - 1):
         a, b = (_as_int(v, 4) for v in pairs[i])
         c = _as_int(outs[i].cpu().numpy().view(np.uint32), 4)
@@ -246,8 +289,7 @@ def bigmul(args):
     cpu_s = _time.perf_counter() - t0
     return {"metric": "large-integer products/s, 2^20-limb (32 Mbit) operands", "unit": "products/s",
             "value": res["lazy"]["products_per_s"], "workload": "16 products of 2^20 x 2^20 base-2^32 limbs",
-            "lazy": res["lazy"], "plain": res["plain"],
-            "lazy_over_plain": res["plain"]["ms_per_batch"] / res["lazy"]["ms_per_batch"],
+            **res, **_ratios(res, "ms_per_batch"),
             "cpu_python_int": {"seconds": cpu_s, "sample": "one product of 2^19 x 2^19 limbs (16 Mbit operands), "
                                "CPython integer multiplication, 1 core"}}
 

@@ -719,6 +719,14 @@ __device__ __forceinline__ int copyout_chunk(int q) {
   }
 }
 
+// An exchange through LDS among the lanes of one wave: the wave's LDS operations
+// complete in order, so only the compiler must be kept from moving them across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Padded LDS words per sub-transform (rows: row pitch; cols: rows of the tile).
 template <bool Cols>
 constexpr int padded_len(int N) {
@@ -812,6 +820,8 @@ __global__ void __launch_bounds__(kMaxPassThreads)
     // that round (Fold) and, where the row tile's pads hold them, read the high
     // factors from LDS.
     constexpr bool kFold = TT && !Cols && KH > 0 && (kInverse || kFwdFold);
+    // rows whose threads all belong to one wave (consecutive thread ids)
+    constexpr bool kRowInWave = !Cols && TPT <= 64;
     // The rows of one wave read the same factor index at once; their pads would sit
     // in the same bank (the row pitch is a multiple of 64 words), so row g's factors
     // start (g mod rows-per-wave) pad blocks later: 36 words, i.e. another bank.
@@ -1009,7 +1019,11 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio, staged);
           else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio, staged);
         }
-        __syncthreads();
+        // A row no wider than a wave exchanges among that wave's lanes only (its tile
+        // and pads are its own), and nothing writes the shared twiddle table again
+        // unless the pass goes on to a fused inverse.
+        if constexpr (kRowInWave && !FUSE) wave_lds_sync();
+        else __syncthreads();
         if constexpr (KM > 0) {
           round_k<Pol, N_LOG, KM, false>(KL, t, TPT, tws, twg, m, lio, lio);
           __syncthreads();
@@ -1044,7 +1058,8 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           // stores would put neighbouring lanes 2^KL words apart.  Stage them in LDS
           // and write the tile out with consecutive lanes on consecutive 16 bytes.
           round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, lio, lio);
-          __syncthreads();
+          if constexpr (kRowInWave) wave_lds_sync();
+          else __syncthreads();
           // (every thread moves kPer vectors of its row; the partner words of the fused
           // product are all requested before the first is used)
           constexpr int kPitch = padded_len<false>(N);

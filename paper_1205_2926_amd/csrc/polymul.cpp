@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "hntt.h"
@@ -131,6 +132,8 @@ struct hntt_polymul_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool graph_failed = false;
+  std::string graph_error;  // why recording the graph failed
+  int exec_mode = HNTT_EXEC_NONE;
   std::vector<hntt_poly_desc> descs;  // for the one-shot cache
 };
 
@@ -483,28 +486,54 @@ int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *pl, void *stream
   } restore{prev};
   hipStream_t s = (hipStream_t)stream;
   const bool use_graph = !(pl->flags & HNTT_NO_GRAPH) && !pl->graph_failed && !ctx->trace;
-  if (!use_graph) return enqueue_plan(pl, s);
+  if (!use_graph) {
+    pl->exec_mode = pl->graph_failed ? HNTT_EXEC_CAPTURE_FAILED : HNTT_EXEC_DIRECT;
+    return enqueue_plan(pl, s);
+  }
   if (!pl->exec) {
     // record every launch once on a private stream, then replay the graph on the caller's stream
     hipStream_t cs = nullptr;
-    bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
-    int rc = ok ? enqueue_plan(pl, cs) : HNTT_EDEVICE;
+    const char *step = "hipStreamCreateWithFlags";
+    hipError_t he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (he == hipSuccess) {
+      step = "hipStreamBeginCapture";
+      he = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    }
+    int rc = HNTT_OK;
     hipGraph_t g = nullptr;
-    if (ok) ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == HNTT_OK;
-    if (ok) ok = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (he == hipSuccess) {
+      rc = enqueue_plan(pl, cs);
+      step = "hipStreamEndCapture";
+      he = hipStreamEndCapture(cs, &g);
+      if (he == hipSuccess && rc != HNTT_OK) step = "enqueue under capture";
+    }
+    if (he == hipSuccess && rc == HNTT_OK) {
+      step = "hipGraphInstantiate";
+      he = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+    }
     if (cs) (void)hipStreamDestroy(cs);
-    if (!ok) {
+    if (he != hipSuccess || rc != HNTT_OK) {
+      // launch directly from now on, and say why (hntt_polymul_plan_exec_mode)
+      pl->graph_error = std::string(step) + ": " +
+                        (he != hipSuccess ? hipGetErrorString(he) : ctx->last_error.c_str());
       if (g) (void)hipGraphDestroy(g);
       pl->exec = nullptr;
       pl->graph_failed = true;
       (void)hipGetLastError();
       ctx->last_error.clear();
+      pl->exec_mode = HNTT_EXEC_CAPTURE_FAILED;
       return enqueue_plan(pl, s);
     }
     pl->graph = g;
   }
+  pl->exec_mode = HNTT_EXEC_GRAPH;
   return hip_err(ctx, hipGraphLaunch(pl->exec, s), "hipGraphLaunch(polymul)");
+}
+
+int hntt_polymul_plan_exec_mode(const hntt_polymul_plan *pl, const char **msg) {
+  if (!pl) return HNTT_EINVAL;
+  if (msg) *msg = pl->graph_error.c_str();
+  return pl->exec_mode;
 }
 
 void hntt_polymul_plan_destroy(hntt_polymul_plan *pl) {

@@ -81,6 +81,7 @@ SIGNATURES = {
     "hntt_polymul_plan_create": (ctypes.c_int, [_c_vp, ctypes.POINTER(PolyDesc), ctypes.c_size_t, _c_u32, _c_vp,
                                                 ctypes.c_size_t, _c_vp, ctypes.POINTER(_c_vp)]),
     "hntt_polymul_plan_workspace_bytes": (ctypes.c_size_t, [_c_vp]),
+    "hntt_polymul_plan_exec_mode": (ctypes.c_int, [_c_vp, ctypes.POINTER(ctypes.c_char_p)]),
     "hntt_polymul_plan_execute": (ctypes.c_int, [_c_vp, _c_vp, _c_vp]),
     "hntt_polymul_workspace_size": (ctypes.c_int, [ctypes.POINTER(PolyDesc), ctypes.c_size_t,
                                                    ctypes.POINTER(ctypes.c_size_t)]),
@@ -221,6 +222,19 @@ class PolymulPlan:
     def execute(self, stream=None):
         self.ctx._check(self.ctx.lib.hntt_polymul_plan_execute(self.ctx.handle, self.handle,
                                                                _stream_handle(stream, self.device)))
+
+    EXEC_MODES = {0: "not executed", 1: "graph", 2: "direct", 3: "direct (graph capture failed)"}
+
+    @property
+    def exec_mode(self) -> str:
+        """How the last execution was enqueued: graph, direct, or direct after a failed capture (with
+        the reason)."""
+        msg = ctypes.c_char_p()
+        mode = int(self.ctx.lib.hntt_polymul_plan_exec_mode(self.handle, ctypes.byref(msg)))
+        text = self.EXEC_MODES.get(mode, str(mode))
+        if mode == 3 and msg.value:
+            text += ": " + msg.value.decode()
+        return text
 
     def destroy(self):
         if getattr(self, "handle", None):

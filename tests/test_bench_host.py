@@ -79,3 +79,18 @@ def test_workload_product_check_accepts_products_and_rejects_corruption():
             bad[k] += np.uint64(1)
             assert not bw._product_ok(a, b, bad)
         assert not bw._product_ok(a, b, c[:-1])
+
+
+def test_polymul_tuning_cache_key_follows_length_classes():
+    # the cached schedule of a product batch is reused only for a batch with the same
+    # number of products in every length class, of the same kind and policy
+    import torch
+    from paper_1205_2926_amd import autotune
+    t = lambda n: torch.empty(n, dtype=torch.int32)
+    a = [(t(100), t(3)), (t(1000), t(1000)), (t(129), t(1))]
+    b = [(t(1), t(70)), (t(513), t(600)), (t(200), t(65))]  # same classes (2^8, 2^11, 2^9)
+    c = [(t(100), t(3)), (t(1000), t(1000)), (t(1000), t(1))]
+    assert autotune._poly_key(a, False, False) == autotune._poly_key(b, False, False)
+    assert autotune._poly_key(a, False, False) != autotune._poly_key(c, False, False)
+    assert autotune._poly_key(a, False, False) != autotune._poly_key(a, True, False)
+    assert autotune._poly_key(a, False, False) != autotune._poly_key(a, False, True)
