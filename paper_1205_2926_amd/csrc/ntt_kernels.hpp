@@ -40,7 +40,6 @@ struct SlotParams {
   uint64_t scale_w;   // kWhole inverse: L^-1 (Montgomery policy: L^-1 beta mod p)
   uint64_t scale_wp;  // and its Shoup constant (unused by the Montgomery policy)
   uint64_t jinv;      // p^-1 mod beta (Montgomery policy; fused pointwise product)
-  uint64_t r2;        // beta^2 mod p (fused pointwise product)
   // fused forward + inverse launch (PassParams::fuse_inverse): the inverse
   // transform's per-stage table and split-twiddle factors of the same sub-transform
   const void *tw2;
@@ -123,9 +122,12 @@ struct PassParams {
   uint64_t jinv;      // Montgomery policy: p^-1 mod beta
   // Final forward pass only: when nonzero, every output word is multiplied by the
   // word at the same position of the "partner" transform that starts pm_off words
-  // before this one, and the product (fully reduced) replaces the partner's word
-  // (this transform's own words are left stale).  Used by the polynomial product:
-  // B_k's last pass multiplies into A_k.
+  // before this one, and the product replaces the partner's word (this transform's
+  // own words are left stale).  Used by the polynomial product: B_k's last pass
+  // multiplies into A_k.  The partner's words must be fully reduced and carry a
+  // factor beta (its operand was prepared times beta mod p): the product is one
+  // Montgomery product, in [0,2p) (lazy policy) or [0,p) (plain), the input range
+  // of the inverse transform that follows.
   uint32_t pm_off;
   // With pm_off, 32-bit words, a table and a Shoup policy only: instead of writing
   // the product, run the inverse transform's row pass (kRows) or whole transform

@@ -401,11 +401,15 @@ struct KernelArgs {
   SlotParams slots[kMaxSlots];
 };
 
-// The fused pointwise product of a final forward pass: a b mod p for a, b in [0,p),
-// as two Montgomery products (a b beta^-1, then times beta^2 beta^-1), fully reduced.
-__device__ __forceinline__ T pmul_word(T a, T b, const Mod &m, T r2) {
-  const T u = csub<T>(mont_lazy<Wd>(a, b, m.p, m.j), m.p);
-  return csub<T>(mont_lazy<Wd>(u, r2, m.p, m.j), m.p);
+// The fused pointwise product of a final forward pass: x times the partner's word
+// ab = A beta mod p in [0,p) (the partner operand was prepared times beta, so its
+// transform carries the factor beta), for any x < beta: one Montgomery product
+// x ab beta^-1 = x A mod p, in (0,2p), which the lazy inverse accepts as it is;
+// the plain policy reduces it to [0,p).
+template <int Pol>
+__device__ __forceinline__ T pmul_word(T x, T ab, const Mod &m) {
+  const T u = mont_lazy<Wd>(x, ab, m.p, m.j);
+  return Pol == kPolicyPlain ? csub<T>(u, m.p) : u;
 }
 
 // Split-twiddle factors held in the pad words of an LDS row tile (four pad words
@@ -430,7 +434,6 @@ struct FusedMid {
   const HNTT_GLOBAL T *a_sub;                     // A's words of this sub-transform
   const HNTT_GLOBAL TwT<Pol> *__restrict__ twg_i;  // inverse per-stage table
   Mod m;
-  T r2;
   __device__ __forceinline__ void operator()(T (&v)[1 << K], int base) const {
     constexpr int M = 1 << K;
     if constexpr (M >= kVec) {
@@ -441,11 +444,11 @@ struct FusedMid {
       for (int e = 0; e < M; e += kVec) {
         const T *w = reinterpret_cast<const T *>(&q[e / kVec]);
 #pragma unroll
-        for (int i = 0; i < kVec; ++i) v[e + i] = pmul_word(v[e + i], w[i], m, r2);
+        for (int i = 0; i < kVec; ++i) v[e + i] = pmul_word<Pol>(v[e + i], w[i], m);
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < M; ++e) v[e] = pmul_word(v[e], a_sub[base + e], m, r2);
+      for (int e = 0; e < M; ++e) v[e] = pmul_word<Pol>(v[e], a_sub[base + e], m);
     }
     round_stages<Pol, N_LOG, K, true, true>(v, 0, base, nullptr, twg_i, m, NoFold{});
   }
@@ -479,6 +482,7 @@ template <int Pol, bool Cols, bool TT, int N_LOG, int SIGMA, int Out = kOutAny, 
           bool INV = kInverse>
 struct Edge {
   static constexpr bool kInv = INV;
+  static constexpr int kPol = Pol;
   Mod m;
   int normalize, scale;
   T sw, swp;
@@ -548,7 +552,6 @@ struct GlobalIO {
   static constexpr bool kContig = !Cols;
   HNTT_GLOBAL T *base;
   HNTT_GLOBAL T *pm;            // rows/whole forward: partner base of the fused product, or null
-  T r2;
   __amdgpu_buffer_rsrc_t rsrc;  // Cols: the transform as a buffer
   uint32_t off;
   uint32_t stride;
@@ -559,7 +562,6 @@ struct GlobalIO {
     GlobalIO<Cols, decltype(edge.template with_out<O>())> g;
     g.base = base;
     g.pm = pm;
-    g.r2 = r2;
     g.rsrc = rsrc;
     g.off = off;
     g.stride = stride;
@@ -580,7 +582,7 @@ struct GlobalIO {
     if constexpr (!Cols && !EdgeT::kInv) {  // (the fused product ends forward transforms only)
       if (pm) {
         HNTT_GLOBAL T *q = pm + off + (uint32_t)(lp + up);
-        *q = pmul_word(x, *q, edge.m, r2);
+        *q = pmul_word<EdgeT::kPol>(x, *q, edge.m);
         return;
       }
     }
@@ -608,7 +610,7 @@ struct GlobalIO {
       const Vec16 pa = *dst;
       const T *pw = reinterpret_cast<const T *>(&pa);
 #pragma unroll
-      for (int i = 0; i < kVec; ++i) w[i] = pmul_word(w[i], pw[i], edge.m, r2);
+      for (int i = 0; i < kVec; ++i) w[i] = pmul_word<EdgeT::kPol>(w[i], pw[i], edge.m);
       *dst = q;
       return;
     }
@@ -840,7 +842,6 @@ __global__ void __launch_bounds__(kMaxPassThreads)
       edge.tt = make_rsrc((const void *)uniform64((uint64_t)sp.tt), (1u << a.log_other) * kTTStride * kTw);
     gio.base = gbase;
     gio.pm = a.pm_off ? gbase - a.pm_off : nullptr;
-    gio.r2 = (T)sp.r2;
     if constexpr (Cols) {
       const uint32_t col = (uint32_t)unit * G + g;
       gio.rsrc = make_rsrc((const void *)gbase, (uint32_t)(C * N * sizeof(T)));
@@ -907,16 +908,10 @@ __global__ void __launch_bounds__(kMaxPassThreads)
       HNTT_GLOBAL T *const abase = gbase - a.pm_off;
       gio_a.base = abase;
       gio_a.pm = nullptr;
-      gio_a.r2 = (T)sp.r2;
       gio_a.off = row * N;
       gio_a.stride = 1;
       gio_a.edge = edge_i;
-      if constexpr (kFoldI) {
-        const uint32_t lo = (uint32_t)t & ((1u << SIGMA) - 1);
-        fold_i.a = buf_load_tw<Pol>(edge_i.tt, edge_i.tt_off + lo * kTw, 0);
-        fold_i.aw = buf_load_tw<Pol>(edge_i.tt, edge_i.tt_off + ((1u << SIGMA) + (1u << (N_LOG - SIGMA)) + lo) * kTw, 0);
-      }
-      fmid = FusedMid<Pol, N_LOG, KL>{abase + (size_t)row * N, twg_i, m, (T)sp.r2};
+      fmid = FusedMid<Pol, N_LOG, KL>{abase + (size_t)row * N, twg_i, m};
     }
     const auto hi_store = [&]() {
       if constexpr (kHiLds) {
@@ -1037,6 +1032,11 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           stage_i.nthr = nthr;
           stage_i.load(twg_i);
           hi_load_from(edge_i.tt);
+          if constexpr (kFoldI) {  // the thread's low factor of the inverse (its loads start here)
+            const uint32_t lo = (uint32_t)t & ((1u << SIGMA) - 1);
+            fold_i.a = buf_load_tw<Pol>(edge_i.tt, edge_i.tt_off + lo * kTw, 0);
+            fold_i.aw = buf_load_tw<Pol>(edge_i.tt, edge_i.tt_off + ((1u << SIGMA) + (1u << (N_LOG - SIGMA)) + lo) * kTw, 0);
+          }
           round_k<Pol, N_LOG, KL, true, false, LdsIO<false>, LdsIO<false>, NoHook, NoFold, false>(
               0, t, TPT, tws, twg, m, lio, lio, NoHook{}, NoFold{}, fmid);
           stage_i.store(tws, twg_i);
@@ -1091,7 +1091,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
               const T *pw = reinterpret_cast<const T *>(&pa[j]);
               T *wo = reinterpret_cast<T *>(&o[j]);
 #pragma unroll
-              for (int e = 0; e < kVec; ++e) wo[e] = pmul_word(wo[e], pw[e], m, gio.r2);
+              for (int e = 0; e < kVec; ++e) wo[e] = pmul_word<Pol>(wo[e], pw[e], m);
             }
           }
 #pragma unroll
@@ -1261,7 +1261,7 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   if (pp.table) {
     for (int i = 0; i < pp.nslots; ++i) a.slots[i] = pp.slots[i];
   } else {
-    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp, pp.jinv, 0, nullptr, nullptr};
+    a.slots[0] = SlotParams{pp.p, pp.tw, pp.tt, pp.scale_w, pp.scale_wp, pp.jinv, nullptr, nullptr};
   }
   const int blocks = (int)total;
   using namespace HNTT_NS;

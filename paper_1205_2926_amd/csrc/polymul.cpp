@@ -45,12 +45,6 @@ int hip_err(hntt_ctx *ctx, hipError_t e, const char *what) {
   return perr(ctx, e == hipErrorOutOfMemory ? HNTT_ENOMEM : HNTT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-uint32_t inv_mod_2_32(uint32_t q) {  // q^-1 mod 2^32 (q odd), Newton iteration
-  uint32_t x = q;
-  for (int i = 0; i < 5; ++i) x *= 2u - q * x;
-  return x;
-}
-
 uint32_t shoup32(uint64_t w, uint64_t q) { return (uint32_t)shoup_constant(w, q, 32); }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -173,7 +167,6 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
       sp.scale_w = t.linv;
       sp.scale_wp = t.linv_p;
       sp.jinv = t.jinv;
-      sp.r2 = (uint64_t)(((u128)1 << 64) % kPrimes[k]);
       sp.tt = nullptr;
       sp.tw2 = sp.tt2 = nullptr;
       // the split twiddle belongs to the row pass (both directions)
@@ -402,8 +395,8 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
   a.chunk_carry = reinterpret_cast<uint32_t *>(pl->arena + sz.off_carry);
   for (int k = 0; k < 3; ++k) {
     const uint64_t q = kPrimes[k];
-    const uint64_t r = (uint64_t)(((u128)1 << 64) % q);
-    a.primes[k] = PrimeConst{(uint32_t)q, shoup32(1, q), inv_mod_2_32((uint32_t)q), (uint32_t)r};
+    const uint32_t beta = (uint32_t)((1ull << 32) % q);
+    a.primes[k] = PrimeConst{(uint32_t)q, shoup32(1, q), beta, shoup32(beta, q)};
   }
   const uint64_t q1 = kPrimes[0], q2 = kPrimes[1], q3 = kPrimes[2];
   const uint64_t c12 = powmod(q1 % q2, q2 - 2, q2), c13 = powmod(q1 % q3, q3 - 2, q3),

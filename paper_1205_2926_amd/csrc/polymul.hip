@@ -36,14 +36,16 @@ __global__ void __launch_bounds__(kThreads) k_poly_prep(PolyArgs args) {
     const uint32_t L = 1u << pp.log2_len;
     uint32_t *ws = args.workspace + pp.ws_off;
     // the lower half only: na, nb <= L / 2, and the first forward pass reads the
-    // upper half as zero without loading it
+    // upper half as zero without loading it.  A is stored times beta = 2^32 mod q,
+    // so that the pointwise product fused into the B transforms' last pass is one
+    // Montgomery product (B A beta beta^-1 = A B).
     for (uint32_t j = ce.start + threadIdx.x; j < ce.start + kChunk && j < L / 2; j += kThreads) {
       const uint32_t av = j < pp.na ? pp.a[j] : 0u;
       const uint32_t bv = j < pp.nb ? pp.b[j] : 0u;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const PrimeConst &pc = args.primes[k];
-        ws[(2 * k) * (size_t)L + j] = reduce_u32(av, pc.q, pc.one_p);
+        ws[(2 * k) * (size_t)L + j] = mulc(av, pc.beta, pc.beta_p, pc.q);
         ws[(2 * k + 1) * (size_t)L + j] = reduce_u32(bv, pc.q, pc.one_p);
       }
     }

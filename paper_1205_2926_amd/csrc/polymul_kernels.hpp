@@ -29,7 +29,8 @@ struct ChunkEntry {
 // Per-prime constants: q, floor(2^32/q) (Shoup constant of 1), q^-1 mod 2^32,
 // 2^64 mod q.
 struct PrimeConst {
-  uint32_t q, one_p, jinv, r2;
+  uint32_t q, one_p;    // q and floor(2^32 / q) (Shoup constant of 1)
+  uint32_t beta, beta_p;  // 2^32 mod q and its Shoup constant
 };
 
 // Garner constants with their Shoup constants: q1^-1 mod q2, q1^-1 mod q3, q2^-1 mod q3.
