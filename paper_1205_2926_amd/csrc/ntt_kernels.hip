@@ -98,11 +98,14 @@ T inv_mod_pow2(T p) {  // p^-1 mod 2^bits for odd p, by Newton iteration
 }  // namespace
 
 size_t pass_lds_bytes(const PassParams &pp) {
-  if (pass_split(pp.n, pp.word_bits, pp.kind == PassKind::kWhole).kh == 0) return 0;
+  const RoundSplit sp = pass_split(pp.n, pp.word_bits, pp.kind == PassKind::kWhole);
+  if (sp.kh == 0) return 0;
   const size_t wb = pp.word_bits / 8;
   const size_t N = (size_t)1 << pp.n;
   // per-stage twiddle table (N pairs) + padded tile (see LdsIO in ntt_pass.hip)
-  const size_t padded = pp.kind == PassKind::kCols ? N + N / 32 : row_padded_len(N);
+  const size_t padded = pp.kind == PassKind::kCols
+                            ? N + N / 32
+                            : row_padded_len(N) + row_skew(pp.n, sp.kh, sp.km, sp.kl, pp.word_bits);
   // (no LDS copy of the twiddle table where tw_global says so)
   const size_t bytes = wb * ((tw_global(pp.n, pp.word_bits) ? 0 : 2 * N) + padded * pp.group);
   return bytes <= 160 * 1024 ? bytes : 0;

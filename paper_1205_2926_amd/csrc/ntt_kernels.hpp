@@ -88,6 +88,16 @@ inline RoundSplit pass_split(int n, int word_bits, bool whole = false) {
 // also spare the copy out of the tile its few two-way conflicts, put conflicts
 // into the low round: three times the conflict cycles, measured.)
 constexpr size_t row_padded_len(size_t N) { return N + (N >> 5) * 4; }
+// Extra words between consecutive row tiles of 32-bit words when a row has fewer
+// than 32 threads (TPT = 2^(n - largest round)): the 32-bit LDS accesses of one
+// half-wave (32 lanes, 32 banks) then cover several rows, and shifting each row
+// by TPT words puts their lanes on disjoint banks (the padded pitch alone is a
+// multiple of 32 words).
+constexpr size_t row_skew(int n, int kh, int km, int kl, int word_bits) {
+  const int kmax = kh > km ? (kh > kl ? kh : kl) : (km > kl ? km : kl);
+  const int tpt = 1 << (n - kmax);
+  return (word_bits == 32 && kh > 0 && tpt < 32) ? (size_t)tpt : 0;
+}
 
 // Whether the rounds of a pass over 2^n-word sub-transforms that do not have
 // compile-time twiddles read them from global memory (L1/L2) instead of an LDS

@@ -721,6 +721,32 @@ __device__ __forceinline__ int copyout_chunk(int q) {
   }
 }
 
+// The chunk that thread t of row g moves in step j of a row pass's copy-out (the
+// tile read from LDS with 16-byte loads, written out with eight lanes on each 128
+// contiguous bytes).  A 16-byte LDS read serves 16 lanes per cycle on 64 banks:
+// four quads of four lanes, the quads of one half-wave whose lane bits 2-4 have the
+// same parity.  With 32 threads per row (2^10 words), the four 8-lane segments of
+// step j take 32-word blocks j, j + 16, j + 8 and j + 24, whose bank offsets (36
+// words per block) are x, x, x + 32, x + 32: each quad group then covers the 64
+// banks once.  With 16 threads per row (2^9 words: two rows per half-wave, rows
+// TPT words apart) the segments take blocks j and j + 8, turned by 12 blocks in
+// odd rows, and with 2^8 words blocks j and j + 4, turned by 4.  Other shapes keep
+// copyout_chunk's order.
+template <int kChunks, int TPT>
+__device__ __forceinline__ int copyout_row_chunk(int t, int j, int g) {
+  if constexpr (kVec == 4 && TPT == 32 && kChunks == 256) {
+    const int k = t >> 3;
+    const int perm = ((k & 1) << 1) | (k >> 1);  // 0, 2, 1, 3
+    return ((j + 8 * perm) << 3) | (t & 7);
+  } else if constexpr (kVec == 4 && TPT == 16 && (kChunks == 128 || kChunks == 64)) {
+    constexpr int kBlk = kChunks / 8, kPerSeg = kBlk / 2, kTurn = kChunks == 128 ? 12 : 4;
+    const int blk = (j + kPerSeg * (t >> 3) + kTurn * (g & 1)) & (kBlk - 1);
+    return (blk << 3) | (t & 7);
+  } else {
+    return copyout_chunk<kChunks>(t + j * TPT);
+  }
+}
+
 // An exchange through LDS among the lanes of one wave: the wave's LDS operations
 // complete in order, so only the compiler must be kept from moving them across.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -832,7 +858,8 @@ __global__ void __launch_bounds__(kMaxPassThreads)
     constexpr bool kHiLds = TT && !Cols && KH > 0 && (kInverse || kFwdHiLds) &&
                             (1 << KH) + (kRowsPerWave - 1) * kPadTw <= (N / 32) * kPadTw;
     using EdgeT = Edge<Pol, Cols, TT, N_LOG, SIGMA, kOutAny, !kFold, kHiLds>;
-    constexpr int kPitchT = padded_len<Cols>(N);
+    // LDS pitch of a row tile (columns: of a column segment)
+    constexpr int kPitchT = padded_len<Cols>(N) + (Cols ? 0 : (int)row_skew(N_LOG, KH, KM, KL, 8 * sizeof(T)));
     EdgeT edge{m, a.normalize, a.scale, (T)sp.scale_w, (T)sp.scale_wp, make_rsrc(sp.tt, 0), 0, nullptr};
     GlobalIO<Cols, EdgeT> gio;
     constexpr uint32_t kTw = sizeof(TwT<Pol>);
@@ -949,14 +976,14 @@ __global__ void __launch_bounds__(kMaxPassThreads)
       stage.nthr = nthr;
       stage.load(twg);
       hi_load();
-      const LdsIO<Cols> lio{tile, G, g, padded_len<Cols>(N)};
+      const LdsIO<Cols> lio{tile, G, g, kPitchT};
       if constexpr (!kInverse) {
         // Rows with fewer than 32 threads per row: a high-round load instruction would
         // cover under 128 bytes of each row, so the tile is first copied into LDS with
         // consecutive lanes on consecutive 16 bytes, and the high round reads it there.
         constexpr bool kCopyIn = !Cols && TPT < 32;
         if constexpr (kCopyIn) {
-          constexpr int kPitch = padded_len<false>(N);
+          constexpr int kPitch = kPitchT;
           constexpr int kChunks = N / kVec;
           constexpr int kPer = kChunks / TPT;  // vectors per thread
           static_assert(kPer * TPT == kChunks && kPer % 2 == 0, "copy-in covers the tile exactly");
@@ -1062,7 +1089,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           else __syncthreads();
           // (every thread moves kPer vectors of its row; the partner words of the fused
           // product are all requested before the first is used)
-          constexpr int kPitch = padded_len<false>(N);
+          constexpr int kPitch = kPitchT;
           constexpr int kChunks = N / kVec;
           constexpr int kPer = kChunks / TPT;
           static_assert(kPer * TPT == kChunks, "copy-out covers the tile exactly");
@@ -1072,7 +1099,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           Vec16 o[kPer];
 #pragma unroll
           for (int j = 0; j < kPer; ++j) {
-            const int c = copyout_chunk<kChunks>(t + j * TPT) * kVec;
+            const int c = copyout_row_chunk<kChunks, TPT>(t, j, g) * kVec;
             const Vec16 q = *reinterpret_cast<const Vec16 *>(tile + g * kPitch + c + ((c >> 5) << 2));
             const T *w = reinterpret_cast<const T *>(&q);
             T *wo = reinterpret_cast<T *>(&o[j]);
@@ -1085,7 +1112,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
 #pragma unroll
             for (int j = 0; j < kPer; ++j)
               pa[j] = *reinterpret_cast<const HNTT_GLOBAL Vec16 *>(out0 + (size_t)g * N +
-                                                                    copyout_chunk<kChunks>(t + j * TPT) * kVec);
+                                                                    copyout_row_chunk<kChunks, TPT>(t, j, g) * kVec);
 #pragma unroll
             for (int j = 0; j < kPer; ++j) {
               const T *pw = reinterpret_cast<const T *>(&pa[j]);
@@ -1096,7 +1123,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           }
 #pragma unroll
           for (int j = 0; j < kPer; ++j)
-            *reinterpret_cast<HNTT_GLOBAL Vec16 *>(out0 + (size_t)g * N + copyout_chunk<kChunks>(t + j * TPT) * kVec) =
+            *reinterpret_cast<HNTT_GLOBAL Vec16 *>(out0 + (size_t)g * N + copyout_row_chunk<kChunks, TPT>(t, j, g) * kVec) =
                 o[j];
         }
       } else {
