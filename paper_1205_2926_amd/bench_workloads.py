@@ -17,6 +17,9 @@ exactly or modulo two 61-bit primes, and numpy's own modular product.
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 import random
 import sys
 import time
@@ -61,6 +64,59 @@ def _events_ms(fn, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+_TRAFFIC = os.path.join(_ROOT, "profiles", "hbm_traffic_workloads.json")
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 int32 lanes x 2.4 GHz
+
+
+def _counters(workload):
+    """The committed rocprofv3 figures of a workload (HBM bytes and VALU instructions per batch
+    or per launch), or None when the kernel sources changed since they were taken."""
+    try:
+        rec = json.load(open(_TRAFFIC))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(_ROOT, f), "rb").read())
+    except (OSError, ValueError, KeyError):
+        return None
+    return rec["workloads"].get(workload) if h.hexdigest() == rec["source_sha256"] else None
+
+
+def _batch_roofline(workload, ms, butterflies):
+    """Roofline of a whole product batch: the algorithmic VALU work (9 int32 operations per
+    butterfly of Algorithm 3, the CRT and products not counted) against the int32 VALU peak,
+    and the HBM bytes the committed counters recorded for one batch against the 8 TB/s peak;
+    `bound` is the larger fraction (HBM only when the counters are current)."""
+    alu = butterflies * 9 / (ms * 1e-3) / 1e12
+    rec = _counters(workload)
+    out = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": alu / VALU_PEAK_TOPS,
+           "traffic": None, "basis": "butterflies x 9 int32 ops per batch / batch time"}
+    if rec:
+        gbs = rec["bytes_per_batch"] / (ms * 1e-3) / 1e9
+        out["traffic"] = rec["bytes_per_batch"]
+        out["hbm"] = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                      "basis": "counted HBM bytes per batch (FETCH_SIZE, WRITE_SIZE) / batch time"}
+        out["valu_issue"] = rec["valu_insts_per_batch"] / (256 * 2.4e9 * ms * 1e-3)
+        if gbs / HBM_PEAK_GBS > out["frac"]:
+            out.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "basis": out["hbm"]["basis"]})
+    return out
+
+
+def _u64_roofline(ms, cfg):
+    """HBM roofline of the 64-bit batch: four passes per forward+inverse step, each reading and
+    writing every 8-byte word once (the traffic of this two-pass design), over the step time;
+    `traffic` is what the committed counters recorded for the four launches."""
+    words = cfg.batch << cfg.log2_len
+    alg = 4 * words * 16
+    gbs = alg / (ms * 1e-3) / 1e9
+    rec = _counters("u64")
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": sum(rec["bytes_per_launch"].values()) if rec else None,
+            "basis": "4 passes x (8 B read + 8 B written) per word per step / step time"}
 
 
 def _policies(args, all_policies):
@@ -149,7 +205,7 @@ def u64(args):
     ctx.close()
     return {"metric": "NTT butterflies/s, 64-bit words", "unit": "butterflies/s",
             "value": res["lazy"]["butterflies_per_s"], "workload": "8 x 2^22 forward+inverse, p=2^62-ish, u64",
-            "p": p, **res, **_ratios(res, "ms_per_step")}
+            "p": p, **res, **_ratios(res, "ms_per_step"), "roofline": _u64_roofline(res["lazy"]["ms_per_step"], cfg)}
 
 
 def polymul(args):
@@ -182,7 +238,8 @@ def polymul(args):
     return {"metric": "exact polynomial products/s (3 primes + CRT, one graph launch)", "unit": "products/s",
             "value": res["lazy"]["products_per_s"],
             "workload": "4096 pairs, n log-uniform 2^8..2^16, coefficients < 2^20", "sum_padded_len": words,
-            "butterflies_per_batch": bfly, **res, **_ratios(res, "ms_per_batch")}
+            "butterflies_per_batch": bfly, **res, **_ratios(res, "ms_per_batch"),
+            "roofline": _batch_roofline("polymul", res["lazy"]["ms_per_batch"], bfly)}
 
 
 def serving(args):
@@ -287,7 +344,9 @@ def bigmul(args):
     t0 = _time.perf_counter()
     _ = a * b
     cpu_s = _time.perf_counter() - t0
+    bfly = count * 9 * 21 * (1 << 20)  # 9 transforms of 2^21 words per product, 21 x 2^20 butterflies each
     return {"metric": "large-integer products/s, 2^20-limb (32 Mbit) operands", "unit": "products/s",
+            "roofline": _batch_roofline("bigmul", res["lazy"]["ms_per_batch"], bfly),
             "value": res["lazy"]["products_per_s"], "workload": "16 products of 2^20 x 2^20 base-2^32 limbs",
             **res, **_ratios(res, "ms_per_batch"),
             "cpu_python_int": {"seconds": cpu_s, "sample": "one product of 2^19 x 2^19 limbs (16 Mbit operands), "
