@@ -98,10 +98,12 @@ def test_graph_replays_match_eager(ctx, orc):
     outs = [torch.zeros_like(o) for o in outs_e]
     plan = ctx.polymul_plan(dpairs, outs)
     try:
+        assert plan.exec_mode == "not executed"
         for rep in range(4):
             for o in outs:
                 o.zero_()
             plan.execute()
+            assert plan.exec_mode == "graph"  # one graph launch, not the kernel-by-kernel fallback
             torch.cuda.synchronize()
             scratch = torch.arange(1 << 20, device="cuda").sum()  # unrelated eager work between replays
             assert int(scratch) == (1 << 20) * ((1 << 20) - 1) // 2
@@ -111,6 +113,38 @@ def test_graph_replays_match_eager(ctx, orc):
         plan.destroy()
     a, b = pairs[5]
     np.testing.assert_array_equal(eager[5], orc.polymul_exact(a, b, CRT_PRIMES))
+
+
+def test_plan_exec_mode_reports_direct_launches(ctx, orc):
+    """A plan made without the graph, or executed while launches are traced, reports that its
+    kernels were launched one by one, and gives the same products."""
+    pairs = polymul_pairs(seed=46, pairs=8, lo_bits=8, hi_bits=12)
+    dpairs = [(dev(a), dev(b)) for a, b in pairs]
+    outs = [torch.empty(a.size + b.size - 1, dtype=torch.int64, device="cuda") for a, b in pairs]
+    plan = ctx.polymul_plan(dpairs, outs, graph=False)
+    try:
+        plan.execute()
+        assert plan.exec_mode == "direct"
+    finally:
+        plan.destroy()
+    direct = [host(o, np.uint64) for o in outs]
+    plan = ctx.polymul_plan(dpairs, outs)
+    try:
+        ctx.trace(True)
+        plan.execute()
+        torch.cuda.synchronize()
+        ctx.trace(False)
+        assert plan.exec_mode == "direct"  # tracing times each launch, so the graph is not used
+        plan.execute()
+        torch.cuda.synchronize()
+        assert plan.exec_mode == "graph"
+    finally:
+        ctx.trace(False)
+        ctx.trace_reset()
+        plan.destroy()
+    for o, d, (a, b) in zip(outs, direct, pairs):
+        np.testing.assert_array_equal(host(o, np.uint64), d)
+        np.testing.assert_array_equal(d, orc.polymul_exact(a, b, CRT_PRIMES))
 
 
 def test_plan_with_caller_workspace(ctx, orc):
