@@ -49,18 +49,22 @@ def _compile(spec) -> str:
 
 PROBE_SRC = os.path.join(HERE, "probe", "valu_rates.hip")
 PROBE_BIN = os.path.join(HERE, "probe", "valu_rates")
+LDS_PROBE_SRC = os.path.join(HERE, "probe", "lds_banks.hip")
+LDS_PROBE_BIN = os.path.join(HERE, "probe", "lds_banks")
 
 
 def build_probe() -> str:
-    """The instruction-rate, shader-clock and copy-bandwidth probe (a standalone program)."""
-    tmp = PROBE_BIN + ".tmp"
-    cmd = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", PROBE_SRC, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed on the rate probe")
-    os.replace(tmp, PROBE_BIN)
+    """The standalone measurement programs: instruction rates, shader clock and copy
+    bandwidth (valu_rates), and the LDS lane grouping and bank mapping (lds_banks)."""
+    for src, out in ((PROBE_SRC, PROBE_BIN), (LDS_PROBE_SRC, LDS_PROBE_BIN)):
+        tmp = out + ".tmp"
+        cmd = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", src, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc failed on {os.path.basename(src)}")
+        os.replace(tmp, out)
     return PROBE_BIN
 
 
