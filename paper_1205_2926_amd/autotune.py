@@ -28,6 +28,9 @@ from . import hntt
 
 CACHE = os.environ.get("HNTT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hntt", "tune.json"))
 REFINE_TOP, REFINE_ROUNDS, REFINE_REPS = 6, 5, 20
+# a candidate replaces the built-in schedule only when it is faster by more than this
+# fraction (timings of one schedule differ by about a percent from run to run)
+MARGIN = 0.01
 SPACE = {"g_cols": [4, 8, 16, 32, 64], "g_rows": [1, 2, 4, 8, 16, 32, 64], "batch_chunk": [8, 16, 32, 64]}
 
 
@@ -168,6 +171,9 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
         if verbose:
             print(f"  finalist {cand}", flush=True)
     best = min(finalists, key=lambda r: r["ms"]) if finalists else {**default, "ms": None}
+    base = [r for r in finalists if all(r[k] == default[k] for k in ("g_cols", "g_rows", "batch_chunk", "row_log2"))]
+    if base and best["ms"] is not None and best["ms"] > base[0]["ms"] * (1 - MARGIN):
+        best = base[0]  # not measurably faster than the built-in schedule
     _apply(ctx, log2_len, word_bits, best)
     rec = {"best": best, "default": default, "trials": len(trials), "tune_s": time.time() - t0}
     if use_cache:
@@ -253,6 +259,10 @@ def tune_polymul(ctx, pairs, outs, plain: bool = False, reps: int = 3, verbose: 
                 times.setdefault((c, gc, gr), []).append(_plan_ms(plan, reps))
                 plan.destroy()
         best = min(times, key=lambda k: statistics.median(times[k]))
+        dkey = (default["row_log2"], default["g_cols"], default["g_rows"])
+        if dkey in times and dkey in pool and \
+                statistics.median(times[best]) > statistics.median(times[dkey]) * (1 - MARGIN):
+            best = dkey  # not measurably faster than the built-in schedule
         ctx.set_tuning(l, 32, best[1], best[2], 0, best[0])
         chosen[l] = {"row_log2": best[0], "g_cols": best[1], "g_rows": best[2], "ms": statistics.median(times[best]),
                      "default": {k: default[k] for k in ("row_log2", "g_cols", "g_rows")}}
