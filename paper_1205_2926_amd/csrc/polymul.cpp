@@ -104,6 +104,7 @@ int size_batch(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, bool check_
 
 struct ClassWork {
   int l;
+  int ws0, ws1, out0, out1;  // the class's range of preparation and output chunks
   Plan plan;  // the class's split and schedule, fixed when the plan is made
   int nfwd, ninv;               // nfwd: entries of each forward table
   const XformEntry *fwd_a, *fwd_b, *inv;  // device tables inside the arena
@@ -229,25 +230,89 @@ static int run_class(hntt_ctx *ctx, const ClassWork &cw, int which, uint32_t fla
   return HNTT_OK;
 }
 
-static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s) {
+// Parallel branches of a recorded plan (one per length class, up to this many).
+constexpr int kGraphBranches = 4;
+
+// Length classes are independent from the preparation to the CRT.  With `branch`
+// streams (and one fork event and one join event per stream) class i runs on
+// branch[i % nbranch], forked from and joined back into s: recorded into a graph,
+// the classes become parallel branches, so that the short launches of the small
+// classes need not wait for the long ones of the large classes.
+struct Branches {
+  hipStream_t *stream = nullptr;
+  hipEvent_t *fork = nullptr, *join = nullptr;
+  int n = 0;
+};
+
+static int enqueue_plan(hntt_polymul_plan *pl, hipStream_t s, const Branches &br = Branches{}) {
   hntt_ctx *ctx = pl->ctx;
   const PolyArgs &a = pl->args;
   hipError_t e;
   int rc;
-  if ((e = trace_launch(ctx, "poly_prep", s, [&]() { return launch_poly_prep(a, s); })) != hipSuccess)
+  const int nb = br.n > 0 ? std::min<int>(br.n, (int)pl->classes.size()) : 0;
+  // on branches, coefficient products prepare and recombine each class on its own
+  // branch (the preparation and CRT of one class overlap the transforms of others)
+  const bool per_class = nb > 0 && !pl->big;
+  const auto class_args = [&](const ClassWork &cw) {
+    PolyArgs ca = a;
+    ca.chunks_ws = a.chunks_ws + cw.ws0;
+    ca.nchunks_ws = cw.ws1 - cw.ws0;
+    ca.chunks_out = a.chunks_out + cw.out0;
+    ca.nchunks_out = cw.out1 - cw.out0;
+    return ca;
+  };
+  if (!per_class &&
+      (e = trace_launch(ctx, "poly_prep", s, [&]() { return launch_poly_prep(a, s); })) != hipSuccess)
     return hip_err(ctx, e, "launch(poly prep)");
-  for (const ClassWork &cw : pl->classes)
-    if ((rc = run_class(ctx, cw, 0, pl->flags, s))) return rc;
-  for (const ClassWork &cw : pl->classes)  // B_k transforms; their last pass multiplies into A_k
-    if ((rc = run_class(ctx, cw, 1, pl->flags, s))) return rc;
-  for (const ClassWork &cw : pl->classes)
-    if ((rc = run_class(ctx, cw, 2, pl->flags, s))) return rc;
+  for (int b = 0; b < nb; ++b) {
+    if ((e = hipEventRecord(br.fork[b], s)) != hipSuccess) return hip_err(ctx, e, "hipEventRecord(fork)");
+    if ((e = hipStreamWaitEvent(br.stream[b], br.fork[b], 0)) != hipSuccess)
+      return hip_err(ctx, e, "hipStreamWaitEvent(fork)");
+  }
+  if (nb) {
+    // largest classes first, each to the branch with the least work so far (work of a
+    // class ~ transforms x L log L); on its branch a class runs its three phases in turn
+    std::vector<size_t> order(pl->classes.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    const auto work = [&](size_t i) {
+      const ClassWork &cw = pl->classes[i];
+      return (double)cw.nfwd * (double)(1ull << cw.l) * cw.l;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
+    std::vector<double> load(nb, 0.0);
+    for (size_t i : order) {
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[b] += work(i);
+      const hipStream_t st = br.stream[b];
+      const PolyArgs ca = class_args(pl->classes[i]);
+      if (per_class &&
+          (e = trace_launch(ctx, "poly_prep", st, [&]() { return launch_poly_prep(ca, st); })) != hipSuccess)
+        return hip_err(ctx, e, "launch(poly prep)");
+      for (int which = 0; which < 3; ++which)
+        if ((rc = run_class(ctx, pl->classes[i], which, pl->flags, st))) return rc;
+      if (per_class &&
+          (e = trace_launch(ctx, "poly_crt", st, [&]() { return launch_poly_crt(ca, st); })) != hipSuccess)
+        return hip_err(ctx, e, "launch(poly crt)");
+    }
+  } else {
+    for (const ClassWork &cw : pl->classes)
+      if ((rc = run_class(ctx, cw, 0, pl->flags, s))) return rc;
+    for (const ClassWork &cw : pl->classes)  // B_k transforms; their last pass multiplies into A_k
+      if ((rc = run_class(ctx, cw, 1, pl->flags, s))) return rc;
+    for (const ClassWork &cw : pl->classes)
+      if ((rc = run_class(ctx, cw, 2, pl->flags, s))) return rc;
+  }
+  for (int b = 0; b < nb; ++b) {
+    if ((e = hipEventRecord(br.join[b], br.stream[b])) != hipSuccess) return hip_err(ctx, e, "hipEventRecord(join)");
+    if ((e = hipStreamWaitEvent(s, br.join[b], 0)) != hipSuccess) return hip_err(ctx, e, "hipStreamWaitEvent(join)");
+  }
   if (pl->big) {
     if ((e = trace_launch(ctx, "big_crt", s, [&]() { return launch_big_crt(a, s); })) != hipSuccess)
       return hip_err(ctx, e, "launch(big crt)");
     if ((e = trace_launch(ctx, "big_carry", s, [&]() { return launch_big_carry(a, s); })) != hipSuccess)
       return hip_err(ctx, e, "launch(big carry)");
-  } else if ((e = trace_launch(ctx, "poly_crt", s, [&]() { return launch_poly_crt(a, s); })) != hipSuccess) {
+  } else if (!per_class &&
+             (e = trace_launch(ctx, "poly_crt", s, [&]() { return launch_poly_crt(a, s); })) != hipSuccess) {
     return hip_err(ctx, e, "launch(poly crt)");
   }
   return HNTT_OK;
@@ -349,12 +414,23 @@ static int plan_create(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uin
   size_t woff = 0, cw_i = 0, co_i = 0;
   for (size_t i = 0; i < n; ++i) {
     const hntt_poly_desc &d = descs[i];
-    const int l = logs[i];
-    hp[i] = PolyPair{d.a, d.b, d.out, d.na, d.nb, (uint32_t)l, (uint32_t)co_i, woff};
-    for (uint64_t s = 0; s < (1ull << l) / 2; s += kChunkWords) hcw[cw_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
-    const uint64_t nout = (uint64_t)d.na + d.nb - (big ? 0 : 1);
-    for (uint64_t s = 0; s < nout; s += kChunkWords) hco[co_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
-    woff += 6ull << l;
+    hp[i] = PolyPair{d.a, d.b, d.out, d.na, d.nb, (uint32_t)logs[i], 0, woff};
+    woff += 6ull << logs[i];
+  }
+  // chunk lists grouped by length class, so that each class's chunks are one range
+  for (ClassWork &cw : classes) {
+    cw.ws0 = (int)cw_i;
+    cw.out0 = (int)co_i;
+    for (size_t i = 0; i < n; ++i) {
+      if (logs[i] != cw.l) continue;
+      const hntt_poly_desc &d = descs[i];
+      hp[i].chunk0 = (uint32_t)co_i;
+      for (uint64_t s = 0; s < (1ull << cw.l) / 2; s += kChunkWords) hcw[cw_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
+      const uint64_t nout = (uint64_t)d.na + d.nb - (big ? 0 : 1);
+      for (uint64_t s = 0; s < nout; s += kChunkWords) hco[co_i++] = ChunkEntry{(uint32_t)i, (uint32_t)s};
+    }
+    cw.ws1 = (int)cw_i;
+    cw.out1 = (int)co_i;
   }
   // transform tables per length class: forward over A_k, forward over B_k, inverse over A_k
   size_t xi = 0;
@@ -484,10 +560,18 @@ int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *pl, void *stream
     return enqueue_plan(pl, s);
   }
   if (!pl->exec) {
-    // record every launch once on a private stream, then replay the graph on the caller's stream
+    // record every launch once on a private stream (the length classes on branch
+    // streams forked from it), then replay the graph on the caller's stream
     hipStream_t cs = nullptr;
+    hipStream_t bs[kGraphBranches] = {};
+    hipEvent_t fork[kGraphBranches] = {}, join[kGraphBranches] = {};
     const char *step = "hipStreamCreateWithFlags";
     hipError_t he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (int b = 0; b < kGraphBranches && he == hipSuccess; ++b) {
+      he = hipStreamCreateWithFlags(&bs[b], hipStreamNonBlocking);
+      if (he == hipSuccess) he = hipEventCreateWithFlags(&fork[b], hipEventDisableTiming);
+      if (he == hipSuccess) he = hipEventCreateWithFlags(&join[b], hipEventDisableTiming);
+    }
     if (he == hipSuccess) {
       step = "hipStreamBeginCapture";
       he = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
@@ -495,7 +579,7 @@ int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *pl, void *stream
     int rc = HNTT_OK;
     hipGraph_t g = nullptr;
     if (he == hipSuccess) {
-      rc = enqueue_plan(pl, cs);
+      rc = enqueue_plan(pl, cs, Branches{bs, fork, join, kGraphBranches});
       step = "hipStreamEndCapture";
       he = hipStreamEndCapture(cs, &g);
       if (he == hipSuccess && rc != HNTT_OK) step = "enqueue under capture";
@@ -503,6 +587,11 @@ int hntt_polymul_plan_execute(hntt_ctx *ctx, hntt_polymul_plan *pl, void *stream
     if (he == hipSuccess && rc == HNTT_OK) {
       step = "hipGraphInstantiate";
       he = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+    }
+    for (int b = 0; b < kGraphBranches; ++b) {
+      if (fork[b]) (void)hipEventDestroy(fork[b]);
+      if (join[b]) (void)hipEventDestroy(join[b]);
+      if (bs[b]) (void)hipStreamDestroy(bs[b]);
     }
     if (cs) (void)hipStreamDestroy(cs);
     if (he != hipSuccess || rc != HNTT_OK) {
