@@ -182,11 +182,14 @@ int hntt_polymul_crt(hntt_ctx *ctx, const hntt_poly_desc *descs, size_t n, uint3
  * at least hntt_polymul_plan_workspace_bytes of the plan — pass NULL first to
  * learn the size) or allocated by the plan (workspace = NULL).  The descriptor
  * pointers are captured: the operands must stay valid until execution ends.
- * hntt_polymul_plan_execute enqueues only kernel launches (no allocation, no
- * copies, no synchronisation), so it may itself be captured; unless
- * HNTT_NO_GRAPH was given, the launches are recorded into a HIP graph on the
- * first execution and the graph is replayed on `stream` afterwards.  Two
- * executions of one plan must not overlap (they share the workspace).
+ * hntt_polymul_plan_execute enqueues only kernel launches (no device
+ * allocation, no copies, no synchronisation).  Unless HNTT_NO_GRAPH was given,
+ * the first execution records the launches into a HIP graph, on private streams
+ * it creates and destroys for that (each length class on a parallel branch),
+ * and every execution replays the graph on `stream`; with HNTT_NO_GRAPH the
+ * kernels are launched one by one on `stream`, which is the form to use when the
+ * caller itself captures the execution into a graph.  Two executions of one plan
+ * must not overlap (they share the workspace).
  * hntt_polymul_plan_destroy frees what the plan owns; the caller must make sure
  * no enqueued execution still uses it.
  * Errors as for hntt_polymul_crt; ENOMEM if the given workspace is too small. */

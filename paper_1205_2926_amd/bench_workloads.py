@@ -7,6 +7,7 @@ pointwise c = a b mod p over 64 x 2^20 u32 words (HBM roofline of the standalone
 table1    host CPU: Algorithm 2 vs Algorithm 3, one transform of 2^11 over the 62-bit prime
           (the design of the paper's Table 1), time per butterfly on one core
 polymul   4096 products with log-uniform lengths 2^8..2^16, three primes + CRT, one graph launch
+          (each length class a parallel branch of the graph)
 serving   Poisson stream of products (lengths 2^10..2^20), rate swept up to saturation
 Each returns one JSON-able dict.  Inputs are the seeded synthetic workloads of
 ``workloads.py``; results are checked before the numbers are reported, with
