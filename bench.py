@@ -273,7 +273,8 @@ def main():
     # the other policies once more under the lazy schedule: the butterflies alone compared
     same = {}
     sched = schedules["lazy"]
-    ctx.set_tuning(l, cfg.word_bits, sched["g_cols"], sched["g_rows"], sched["batch_chunk"], sched["row_log2"])
+    ctx.set_tuning(l, cfg.word_bits, sched["g_cols"], sched["g_rows"], sched["batch_chunk"], sched["row_log2"],
+                   sched["g_rows_inv"])
     for policy in policies[1:]:
         same[policy] = time_steps(ctx, x, p, w, policy, args.steps, args.warmup)[0]
     # forward and inverse apart, per step, under the lazy schedule

@@ -300,7 +300,8 @@ int hntt_validate(hntt_ctx *ctx, const hntt_desc *descs, size_t n, uint32_t flag
  * runs as a column pass and a row pass (an R x C view, l = log R + log C): the
  * first log R stages of Algorithm 1 (Section 1) are fused into the column pass
  * and the last row_log2 = log C into the row pass.  g_cols / g_rows are the
- * sub-transforms (columns / rows) one workgroup owns in each, and batch_chunk
+ * sub-transforms (columns / rows) one workgroup owns in each (g_rows_inv: rows
+ * per workgroup in the inverse transform's row pass, 0 meaning g_rows), and batch_chunk
  * the number of transforms that go through all passes before the next chunk
  * starts (so a chunk's intermediate result can stay in the last-level cache).
  * Fields set to 0 keep the built-in choice (row_log2: ceil(l / 2); both passes
@@ -317,6 +318,7 @@ typedef struct {
   uint32_t g_rows;
   uint32_t batch_chunk;
   uint32_t row_log2;
+  uint32_t g_rows_inv;
 } hntt_tuning;
 int hntt_set_tuning(hntt_ctx *ctx, const hntt_tuning *t);
 int hntt_get_plan(hntt_ctx *ctx, uint32_t log2_len, uint32_t word_bits, hntt_tuning *out);

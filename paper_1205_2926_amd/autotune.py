@@ -107,7 +107,8 @@ def splits(ctx, log2_len, word_bits):
 
 
 def _apply(ctx, log2_len, word_bits, cand):
-    ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"], cand.get("row_log2", 0))
+    ctx.set_tuning(log2_len, word_bits, cand["g_cols"], cand["g_rows"], cand["batch_chunk"], cand.get("row_log2", 0),
+                   cand.get("g_rows_inv", 0))
 
 
 def candidates(ctx, log2_len, word_bits, batch):
@@ -174,12 +175,50 @@ def tune(ctx, x: torch.Tensor, p: int, omega: int, plain: bool = False, reps: in
     base = [r for r in finalists if all(r[k] == default[k] for k in ("g_cols", "g_rows", "batch_chunk", "row_log2"))]
     if base and best["ms"] is not None and best["ms"] > base[0]["ms"] * (1 - MARGIN):
         best = base[0]  # not measurably faster than the built-in schedule
+    if best.get("ms") is not None and best.get("g_rows"):
+        best = _refine_row_groups(ctx, x, p, omega, policy, log2_len, word_bits, best, reps, verbose)
     _apply(ctx, log2_len, word_bits, best)
     rec = {"best": best, "default": default, "trials": len(trials), "tune_s": time.time() - t0}
     if use_cache:
         cache[key] = rec
         save_cache(cache)
     return rec
+
+
+def _refine_row_groups(ctx, x, p, omega, policy, log2_len, word_bits, best, reps, verbose):
+    """The forward and the inverse row pass may prefer different numbers of rows per
+    workgroup: try half, the same and twice the chosen number for each of them (nine pairs),
+    timed in turn with the chosen schedule, and keep another pair only if it is faster by
+    more than MARGIN."""
+    g = best["g_rows"]
+    cands = [dict(best, g_rows_inv=0)]
+    for gf in (g // 2, g, g * 2):
+        for gi in (g // 2, g, g * 2):
+            if (gf, gi) == (g, g):
+                continue
+            cand = dict(best, g_rows=gf, g_rows_inv=gi)
+            try:
+                _apply(ctx, log2_len, word_bits, cand)
+            except hntt.HnttError:
+                continue
+            cands.append(cand)
+    if len(cands) == 1:
+        _apply(ctx, log2_len, word_bits, best)
+        return best
+    runs = [[] for _ in cands]
+    for _ in range(REFINE_ROUNDS):
+        for i, cand in enumerate(cands):
+            _apply(ctx, log2_len, word_bits, cand)
+            runs[i].append(_time(ctx, x, p, omega, policy, max(reps, REFINE_REPS)))
+    ms = [statistics.median(r) for r in runs]
+    i = min(range(len(cands)), key=lambda k: ms[k])
+    if i and ms[i] > ms[0] * (1 - MARGIN):
+        i = 0
+    if verbose:
+        print(f"  row groups {[(c['g_rows'], c['g_rows_inv'], round(m, 4)) for c, m in zip(cands, ms)]}", flush=True)
+    chosen = dict(cands[i], ms=ms[i])
+    _apply(ctx, log2_len, word_bits, chosen)
+    return chosen
 
 
 def _plan_ms(plan, reps):

@@ -124,7 +124,7 @@ Plan make_plan(int l, int word_bits, int row_log2) {
     pl.split = false;
     pl.r = l;
     pl.c = 0;
-    pl.g_cols = pl.g_rows = 1;
+    pl.g_cols = pl.g_rows = pl.g_rows_inv = 1;
     return pl;
   }
   pl.split = true;
@@ -146,7 +146,7 @@ Plan make_plan(int l, int word_bits, int row_log2) {
   // row pass: up to 512 threads per workgroup (the fastest row-pass shape measured at L = 2^20)
   int gr = std::max(1, kMaxPassThreads / pass_tpt(pl.c, word_bits));
   while (gr > 1 && (gr > (1 << pl.r) || !lds_ok(pl.c, gr))) gr >>= 1;
-  pl.g_rows = gr;
+  pl.g_rows = pl.g_rows_inv = gr;
   pl.chunk = kMaxBatchPerLaunch;
   return pl;
 }
@@ -186,6 +186,11 @@ int check_tuning(const hntt_tuning &t, std::string *why) {
     if (!base.split || !pow2(t.g_rows) || t.g_rows > (1u << base.r) || !fits(PassKind::kRows, base.c, t.g_rows))
       return fail("g_rows must be a power of two that fits the row pass");
   }
+  if (t.g_rows_inv) {
+    if (!base.split || !pow2(t.g_rows_inv) || t.g_rows_inv > (1u << base.r) ||
+        !fits(PassKind::kRows, base.c, t.g_rows_inv))
+      return fail("g_rows_inv must be a power of two that fits the row pass");
+  }
   return HNTT_OK;
 }
 
@@ -195,6 +200,7 @@ Plan effective_plan(const hntt_ctx *ctx, int l, int word_bits) {
   if (it != ctx->tuning.end()) {
     if (it->second.g_cols) pl.g_cols = (int)it->second.g_cols;
     if (it->second.g_rows) pl.g_rows = (int)it->second.g_rows;
+    pl.g_rows_inv = it->second.g_rows_inv ? (int)it->second.g_rows_inv : pl.g_rows;
     if (it->second.batch_chunk) pl.chunk = (int)it->second.batch_chunk;
   }
   return pl;
@@ -454,7 +460,7 @@ int run_transform(hntt_ctx *ctx, const Tables &t, const Plan &plan, const std::v
     rows.kind = PassKind::kRows;
     rows.n = plan.c;
     rows.log_other = plan.r;
-    rows.group = plan.g_rows;
+    rows.group = inverse ? plan.g_rows_inv : plan.g_rows;
     rows.tw = inverse ? t.row_inv : t.row_fwd;
     rows.tt = inverse ? t.tt_inv : t.tt_fwd;
     if (!inverse) {
@@ -664,6 +670,7 @@ int hntt_get_plan(hntt_ctx *ctx, uint32_t log2_len, uint32_t word_bits, hntt_tun
   out->g_rows = pl.split ? (uint32_t)pl.g_rows : 0;
   out->batch_chunk = (uint32_t)pl.chunk;
   out->row_log2 = (uint32_t)pl.c;
+  out->g_rows_inv = pl.split ? (uint32_t)pl.g_rows_inv : 0;
   return HNTT_OK;
 }
 

@@ -30,7 +30,8 @@ struct Plan {
   int r;       // log2 of the column-transform length (split) or l (whole)
   int c;       // log2 of the row length (split)
   int g_cols;  // columns per workgroup in the column pass
-  int g_rows;  // rows per workgroup in the row pass
+  int g_rows;  // rows per workgroup in the row pass (forward; polynomial products)
+  int g_rows_inv;  // rows per workgroup in the inverse transform's row pass
   int chunk;   // transforms per launch; every pass runs on one chunk before the next chunk
 };
 

@@ -56,7 +56,7 @@ class PwDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("log2_len", _c_u32), ("word_bits", _c_u32), ("g_cols", _c_u32), ("g_rows", _c_u32),
-                ("batch_chunk", _c_u32), ("row_log2", _c_u32)]
+                ("batch_chunk", _c_u32), ("row_log2", _c_u32), ("g_rows_inv", _c_u32)]
 
 
 class PolyDesc(ctypes.Structure):
@@ -397,14 +397,14 @@ class Context:
 
     # -- schedule tuning ---------------------------------------------------------------------------
     def set_tuning(self, log2_len: int, word_bits: int, g_cols: int = 0, g_rows: int = 0, batch_chunk: int = 0,
-                   row_log2: int = 0):
-        t = Tuning(log2_len, word_bits, g_cols, g_rows, batch_chunk, row_log2)
+                   row_log2: int = 0, g_rows_inv: int = 0):
+        t = Tuning(log2_len, word_bits, g_cols, g_rows, batch_chunk, row_log2, g_rows_inv)
         self._check(self.lib.hntt_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_plan(self, log2_len: int, word_bits: int) -> dict:
         t = Tuning()
         self._check(self.lib.hntt_get_plan(self.handle, log2_len, word_bits, ctypes.byref(t)))
-        return {k: getattr(t, k) for k in ("g_cols", "g_rows", "batch_chunk", "row_log2")}
+        return {k: getattr(t, k) for k in ("g_cols", "g_rows", "batch_chunk", "row_log2", "g_rows_inv")}
 
     # -- kernel timing -----------------------------------------------------------------------------
     def trace(self, enable: bool = True):

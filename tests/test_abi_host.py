@@ -170,13 +170,17 @@ def test_tuning_overrides_checked_on_host(ctx):
     base = ctx.get_plan(20, 32)
     assert base["g_cols"] >= 1 and base["g_rows"] >= 1 and base["batch_chunk"] == 64
     assert base["row_log2"] == 10  # the built-in split of 2^20: ten stages per pass
+    assert base["g_rows_inv"] == base["g_rows"]  # the inverse row pass follows g_rows unless told otherwise
     ctx.set_tuning(20, 32, g_cols=8, g_rows=2, batch_chunk=16)
-    assert ctx.get_plan(20, 32) == {"g_cols": 8, "g_rows": 2, "batch_chunk": 16, "row_log2": 10}
+    assert ctx.get_plan(20, 32) == {"g_cols": 8, "g_rows": 2, "batch_chunk": 16, "row_log2": 10, "g_rows_inv": 2}
+    ctx.set_tuning(20, 32, g_rows=16, g_rows_inv=8)
+    assert (ctx.get_plan(20, 32)["g_rows"], ctx.get_plan(20, 32)["g_rows_inv"]) == (16, 8)
     # another split of Algorithm 1's stages between the passes: 9 in the row pass, 11 in the column pass
     ctx.set_tuning(20, 32, row_log2=9)
     assert ctx.get_plan(20, 32)["row_log2"] == 9
-    for bad in (dict(g_cols=3), dict(g_cols=64), dict(g_rows=1024), dict(batch_chunk=65), dict(row_log2=13),
-                dict(row_log2=7), dict(row_log2=20)):  # (7 and 20 leave the column pass 13 and 0 stages)
+    for bad in (dict(g_cols=3), dict(g_cols=64), dict(g_rows=1024), dict(g_rows_inv=3), dict(g_rows_inv=1024),
+                dict(batch_chunk=65), dict(row_log2=13), dict(row_log2=7),
+                dict(row_log2=20)):  # (7 and 20 leave the column pass 13 and 0 stages)
         with pytest.raises(hntt.HnttError):
             ctx.set_tuning(20, 32, **bad)
     with pytest.raises(hntt.HnttError):
@@ -185,6 +189,8 @@ def test_tuning_overrides_checked_on_host(ctx):
         ctx.set_tuning(25, 32, g_cols=4)  # beyond the two-pass range
     with pytest.raises(hntt.HnttError):
         ctx.set_tuning(10, 32, g_cols=4)  # one-pass length has no column pass
+    with pytest.raises(hntt.HnttError):
+        ctx.set_tuning(10, 32, g_rows_inv=2)  # nor a row pass
     ctx.set_tuning(20, 32)
     assert ctx.get_plan(20, 32) == base
 

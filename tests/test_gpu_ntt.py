@@ -383,8 +383,18 @@ def test_schedule_independence(ctx, orc, wb, l, policy):
     for c in sorted({k["row_log2"] for k in cands}):
         picks.append(next(k for k in cands if k["row_log2"] == c))
     assert len({k["row_log2"] for k in picks}) == len(splits(ctx, l, wb)) and (l <= 12 or len(splits(ctx, l, wb)) >= 2)
+    # the inverse row pass with another group than the forward one
+    if l > 12:
+        d = dict(picks[0])
+        for gi in (d["g_rows"] // 2, d["g_rows"] * 2):
+            try:
+                ctx.set_tuning(l, wb, d["g_cols"], d["g_rows"], d["batch_chunk"], d["row_log2"], gi)
+            except hntt.HnttError:
+                continue
+            picks.append({**d, "g_rows_inv": gi})
     for cand in picks:
-        ctx.set_tuning(l, wb, cand["g_cols"], cand["g_rows"], cand["batch_chunk"], cand["row_log2"])
+        ctx.set_tuning(l, wb, cand["g_cols"], cand["g_rows"], cand["batch_chunk"], cand["row_log2"],
+                       cand.get("g_rows_inv", 0))
         t = dev(x)
         ctx.ntt_forward(t, p, w, **_kw(policy))
         got = host(t, dt)
