@@ -250,12 +250,14 @@ def serving(args):
     pinned staging).  Saturation throughput is the highest achieved rate while the offered
     rate grows by 1.5x steps (from the rate of a burst queued at time 0) until the server falls
     behind; the offered rate is then swept over fractions of it, reporting achieved products/s,
-    arrival-to-result p50/p99, the fraction of the wall time the GPU had a batch running, and
-    the most batches in flight at once."""
+    arrival-to-result p50/p99, the fraction of the wall time with a batch in flight (copies in,
+    kernels, copies out), the fractions with product kernels, copies in and copies out running,
+    the host<->device bytes per second, and the most batches in flight at once."""
     from .serve import PolymulServer, make_requests
     ctx = hntt.Context(0)
     budget = 8 << 30
-    keys = ("offered_rate", "products_per_s", "p50_ms", "p99_ms", "gpu_busy_frac", "max_inflight")
+    keys = ("offered_rate", "products_per_s", "p50_ms", "p99_ms", "inflight_frac", "kernel_frac", "h2d_frac",
+            "d2h_frac", "h2d_GBs", "d2h_GBs", "max_inflight")
 
     def serve(reqs):
         srv = PolymulServer(ctx, budget)
@@ -295,7 +297,8 @@ def serving(args):
             assert _product_ok(r.a, r.b, r.result[: r.nout]), "served product mismatch"
         return {"products_per_s": mu,
                 "burst": {k: burst[k] for k in ("requests", "products_per_s", "p50_ms", "p99_ms", "batches",
-                                                "gpu_busy_frac", "max_inflight")},
+                                                "inflight_frac", "kernel_frac", "h2d_frac", "d2h_frac",
+                                                "h2d_GBs", "d2h_GBs", "max_inflight")},
                 "saturation_probes": probes,
                 "sweep": [{k: st[k] for k in ("offered_fraction", *keys, "mean_ms", "requests", "batches",
                                               "peak_bytes")} for st in sweep]}

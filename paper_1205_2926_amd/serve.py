@@ -24,7 +24,10 @@ result never depends on what it was batched with: every product is computed
 independently (checked by the tests: alone vs in the mix, bit for bit).
 Latency is arrival -> result on the host (stamped after the copy out of
 staging); ``run`` reports p50/p99, products/s, the most batches that were on
-the GPU at once and the fraction of the run during which any batch was.
+the GPU at once, the fraction of the run during which any batch was in flight,
+and the fractions during which product kernels, copies in and copies out ran
+(from events around each phase on the batch's stream), with the host<->device
+bytes per second.
 """
 from __future__ import annotations
 
@@ -158,6 +161,10 @@ class _Batch:
     event: torch.cuda.Event
     plan: object
     start: torch.cuda.Event
+    k0: torch.cuda.Event   # after the copies in, before the product kernels
+    k1: torch.cuda.Event   # after the product kernels, before the copies out
+    h2d_bytes: int
+    d2h_bytes: int
 
 
 class PolymulServer:
@@ -184,6 +191,11 @@ class PolymulServer:
         self.inflight: list[_Batch] = []
         self.max_inflight = 0
         self.busy_spans: list[tuple[float, float]] = []  # (start, end) ms of each batch on the GPU
+        self.kernel_spans: list[tuple[float, float]] = []  # (start, end) ms of each batch's product kernels
+        self.in_spans: list[tuple[float, float]] = []      # (start, end) ms of each batch's copies in
+        self.out_spans: list[tuple[float, float]] = []     # (start, end) ms of each batch's copies out
+        self.h2d_bytes = 0
+        self.d2h_bytes = 0
         self.t_ref = None                                  # timing event at the start of run()
         self.nbatches = 0
         self.rejected: list[Request] = []
@@ -245,6 +257,9 @@ class PolymulServer:
         if copies:
             list(self.pool.map(pack, copies))
         ws = self.arena_t[doff + io_bytes:doff + dev_bytes]
+        # the plan is built on the host before anything is queued, so that the phase spans
+        # below hold GPU work only
+        plan = self.ctx.polymul_plan(pairs, outs, plain=self.plain, graph=False, workspace=ws, stream=stream)
         with torch.cuda.stream(stream):
             start = torch.cuda.Event(enable_timing=True)
             start.record(stream)
@@ -252,8 +267,11 @@ class PolymulServer:
                 self.arena_t[doff:doff + st_in].copy_(self.host_t[hoff:hoff + st_in], non_blocking=True)
             for dst, src in direct_in:
                 dst.copy_(src, non_blocking=True)
-            plan = self.ctx.polymul_plan(pairs, outs, plain=self.plain, graph=False, workspace=ws, stream=stream)
+            k0 = torch.cuda.Event(enable_timing=True)
+            k0.record(stream)
             plan.execute(stream=stream)
+            k1 = torch.cuda.Event(enable_timing=True)
+            k1.record(stream)
             if st_out:
                 self.host_t[hoff + st_in:hoff + host_bytes].copy_(self.arena_t[doff + all_in:doff + all_in + st_out],
                                                                   non_blocking=True)
@@ -267,7 +285,8 @@ class PolymulServer:
             r.admitted = now
             r.batch = self.nbatches
         self.inflight.append(_Batch(self.nbatches, order, doff, dev_bytes, hoff, host_bytes,
-                                    [out_offs[id(r)] for r in order], stream, ev, plan, start))
+                                    [out_offs[id(r)] for r in order], stream, ev, plan, start, k0, k1,
+                                    all_in, sum(8 * r.nout for r in order)))
         self.max_inflight = max(self.max_inflight, len(self.inflight))
         self.nbatches += 1
         return True
@@ -293,7 +312,13 @@ class PolymulServer:
                 for r in bt.reqs:
                     r.finished = finished
                 if self.t_ref is not None:
-                    self.busy_spans.append((self.t_ref.elapsed_time(bt.start), self.t_ref.elapsed_time(bt.event)))
+                    t = [self.t_ref.elapsed_time(e) for e in (bt.start, bt.k0, bt.k1, bt.event)]
+                    self.busy_spans.append((t[0], t[3]))
+                    self.in_spans.append((t[0], t[1]))
+                    self.kernel_spans.append((t[1], t[2]))
+                    self.out_spans.append((t[2], t[3]))
+                self.h2d_bytes += bt.h2d_bytes
+                self.d2h_bytes += bt.d2h_bytes
                 bt.plan.destroy()
                 self.arena.release(bt.dev_off, bt.dev_bytes)
                 if bt.host_bytes:
@@ -302,10 +327,11 @@ class PolymulServer:
                 done += len(bt.reqs)
         return done
 
-    def _busy_ms(self) -> float:
-        """Time during which at least one batch was on the GPU (union of the batches' spans)."""
+    @staticmethod
+    def _union_ms(spans) -> float:
+        """Length of the union of (start, end) intervals."""
         total, end = 0.0, None
-        for a, b in sorted(self.busy_spans):
+        for a, b in sorted(spans):
             if end is None or a > end:
                 total += b - a
                 end = b
@@ -320,6 +346,8 @@ class PolymulServer:
         pending: deque = deque()
         nxt = 0
         finished = 0
+        self.busy_spans, self.kernel_spans, self.in_spans, self.out_spans = [], [], [], []
+        self.h2d_bytes = self.d2h_bytes = 0
         self.t_ref = torch.cuda.Event(enable_timing=True)
         self.t_ref.record(torch.cuda.current_stream())
         t0 = time.perf_counter()
@@ -357,7 +385,11 @@ class PolymulServer:
                     time.sleep(min(wait, 0.001))
         wall = time.perf_counter() - t0
         torch.cuda.synchronize()
-        busy_ms = self._busy_ms()
+        inflight_ms = self._union_ms(self.busy_spans)
+        wall_ms = wall * 1e3
+        frac = {k: self._union_ms(sp) / wall_ms if wall > 0 else 0.0
+                for k, sp in (("kernel_frac", self.kernel_spans), ("h2d_frac", self.in_spans),
+                              ("d2h_frac", self.out_spans))}
         lat = np.array([r.finished - r.arrival for r in reqs if r.result is not None])
         return {
             "requests": len(reqs),
@@ -370,7 +402,15 @@ class PolymulServer:
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
             "mean_ms": float(lat.mean() * 1e3) if lat.size else None,
             "max_inflight": self.max_inflight,
-            "gpu_busy_frac": busy_ms / (wall * 1e3) if wall > 0 else 0.0,
+            # share of the wall time with at least one batch between its first copy in and
+            # its last copy out (copies and waits on the stream included)
+            "inflight_frac": inflight_ms / wall_ms if wall > 0 else 0.0,
+            # shares of the wall time with at least one batch in each phase: product kernels,
+            # copies in, copies out (a phase's span on a stream includes waits for a copy engine)
+            **frac,
+            # operand and product bytes moved between host and device, per second of wall time
+            "h2d_GBs": self.h2d_bytes / wall / 1e9 if wall > 0 else 0.0,
+            "d2h_GBs": self.d2h_bytes / wall / 1e9 if wall > 0 else 0.0,
             "peak_bytes": self.arena.peak,
             "budget_bytes": self.budget,
             "host_staging_bytes": self.harena.size,

@@ -68,7 +68,11 @@ def test_mixed_stream_within_budget_and_alone_equals_mix(ctx, orc):
     assert stats["peak_bytes"] <= budget
     assert stats["batches"] > 1
     assert stats["max_inflight"] >= 2, stats  # continuous batching: batches overlap on the device
-    assert 0.0 < stats["gpu_busy_frac"] <= 1.0
+    assert 0.0 < stats["inflight_frac"] <= 1.0
+    assert 0.0 < stats["kernel_frac"] <= stats["inflight_frac"] + 1e-6
+    for k in ("h2d_frac", "d2h_frac"):
+        assert 0.0 < stats[k] <= stats["inflight_frac"] + 1e-6
+    assert stats["h2d_GBs"] > 0.0 and stats["d2h_GBs"] > 0.0
     for r in reqs:
         _check(orc, r, full=r.nout < 3000)
     for r, res in zip(reqs, _alone(ctx, reqs, budget)):
