@@ -130,22 +130,31 @@ Plan make_plan(int l, int word_bits, int row_log2) {
   pl.split = true;
   pl.c = row_log2 ? row_log2 : (l + 1) / 2;
   pl.r = l - pl.c;
-  auto lds_ok = [&](int n, int g) {
-    PassParams pp{};
-    pp.word_bits = word_bits;
-    pp.n = n;
-    pp.group = g;
-    const size_t b = pass_lds_bytes(pp);
-    return pass_split(n, word_bits).kh == 0 || (b && b <= 80 * 1024);
+  // a group fits when both directions of its pass fit (the forward row pass may keep
+  // no LDS copy of the twiddle table; the inverse one does)
+  auto lds_ok = [&](PassKind kind, int n, int g) {
+    if (pass_split(n, word_bits).kh == 0) return true;
+    for (const bool inverse : {false, true}) {
+      PassParams pp{};
+      pp.kind = kind;
+      pp.inverse = inverse;
+      pp.word_bits = word_bits;
+      pp.n = n;
+      pp.group = g;
+      const size_t b = pass_lds_bytes(pp);
+      if (!b || b > 80 * 1024) return false;
+    }
+    return true;
   };
   // column pass: adjacent columns per workgroup so that each row segment is at least 64
   // bytes, and at least 256 threads when the column transforms are short
   int g = std::max(word_bits == 32 ? 16 : 8, 256 / pass_tpt(pl.r, word_bits));
-  while (g > 1 && (pass_tpt(pl.r, word_bits) * g > kMaxPassThreads || g > (1 << pl.c) || !lds_ok(pl.r, g))) g >>= 1;
+  while (g > 1 && (pass_tpt(pl.r, word_bits) * g > kMaxPassThreads || g > (1 << pl.c) || !lds_ok(PassKind::kCols, pl.r, g)))
+    g >>= 1;
   pl.g_cols = g;
   // row pass: up to 512 threads per workgroup (the fastest row-pass shape measured at L = 2^20)
   int gr = std::max(1, kMaxPassThreads / pass_tpt(pl.c, word_bits));
-  while (gr > 1 && (gr > (1 << pl.r) || !lds_ok(pl.c, gr))) gr >>= 1;
+  while (gr > 1 && (gr > (1 << pl.r) || !lds_ok(PassKind::kRows, pl.c, gr))) gr >>= 1;
   pl.g_rows = pl.g_rows_inv = gr;
   pl.chunk = kMaxBatchPerLaunch;
   return pl;
@@ -169,26 +178,35 @@ int check_tuning(const hntt_tuning &t, std::string *why) {
   }
   const Plan base = make_plan((int)t.log2_len, (int)t.word_bits, (int)t.row_log2);
   auto pow2 = [](uint32_t v) { return v && !(v & (v - 1)); };
-  auto fits = [&](PassKind kind, int n, uint32_t g) {
-    PassParams pp{};
-    pp.kind = kind;
-    pp.word_bits = (int)t.word_bits;
-    pp.n = n;
-    pp.group = (int)g;
-    const bool lds_ok = pass_split(n, (int)t.word_bits).kh == 0 || pass_lds_bytes(pp) != 0;
+  // whether g sub-transforms per workgroup fit the pass in the given direction(s)
+  auto fits = [&](PassKind kind, int n, uint32_t g, bool fwd, bool inv) {
+    bool lds_ok = true;
+    if (pass_split(n, (int)t.word_bits).kh != 0) {
+      for (const bool inverse : {false, true}) {
+        if (!(inverse ? inv : fwd)) continue;
+        PassParams pp{};
+        pp.kind = kind;
+        pp.inverse = inverse;
+        pp.word_bits = (int)t.word_bits;
+        pp.n = n;
+        pp.group = (int)g;
+        lds_ok = lds_ok && pass_lds_bytes(pp) != 0;
+      }
+    }
     return lds_ok && pass_tpt(n, (int)t.word_bits) * (int)g <= kMaxPassThreads;
   };
   if (t.g_cols) {
-    if (!base.split || !pow2(t.g_cols) || t.g_cols > (1u << base.c) || !fits(PassKind::kCols, base.r, t.g_cols))
+    if (!base.split || !pow2(t.g_cols) || t.g_cols > (1u << base.c) || !fits(PassKind::kCols, base.r, t.g_cols, true, true))
       return fail("g_cols must be a power of two that fits the column pass");
   }
   if (t.g_rows) {
-    if (!base.split || !pow2(t.g_rows) || t.g_rows > (1u << base.r) || !fits(PassKind::kRows, base.c, t.g_rows))
+    if (!base.split || !pow2(t.g_rows) || t.g_rows > (1u << base.r) ||
+        !fits(PassKind::kRows, base.c, t.g_rows, true, t.g_rows_inv == 0))
       return fail("g_rows must be a power of two that fits the row pass");
   }
   if (t.g_rows_inv) {
     if (!base.split || !pow2(t.g_rows_inv) || t.g_rows_inv > (1u << base.r) ||
-        !fits(PassKind::kRows, base.c, t.g_rows_inv))
+        !fits(PassKind::kRows, base.c, t.g_rows_inv, false, true))
       return fail("g_rows_inv must be a power of two that fits the row pass");
   }
   return HNTT_OK;

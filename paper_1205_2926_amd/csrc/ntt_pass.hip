@@ -23,7 +23,8 @@
 // thread issues all of its loads for such an LDS copy before the first wait.
 //
 // Twiddles of the high and middle rounds depend on the thread's low position
-// bits and are read from an LDS copy of the table; twiddles of the low round
+// bits and are read from an LDS copy of the table (from the table in memory, through
+// L1, in forward row passes of 2^10 words and more: tw_global); twiddles of the low round
 // are uniform across the workgroup (their indices are compile-time multiples of
 // 2^(n-1-b)), so they come straight from global memory through scalar loads,
 // and the butterflies whose twiddle is 1 skip the product entirely.  The split
@@ -70,9 +71,6 @@ using Wd = Word64;
 #endif
 using T = typename Wd::T;
 constexpr bool kInverse = HNTT_INVERSE != 0;
-// Sub-transforms whose high and middle rounds read their twiddles from global
-// memory (L1/L2) instead of an LDS copy (tw_global in ntt_kernels.hpp).
-constexpr bool tw_global_here(int n) { return tw_global(n, HNTT_WORD); }
 
 // Global (HBM) address space: lets the compiler emit global_* instead of flat_*
 // memory instructions, which would also count against the LDS wait counter.
@@ -151,6 +149,17 @@ __device__ __forceinline__ TwT<Pol> buf_load_tw(__amdgpu_buffer_rsrc_t r, uint32
 }
 
 // The modulus of a launch: p, 2p and (Montgomery policy) p^-1 mod beta.
+// Where the rounds read the twiddles that are not compile-time: an LDS copy of the
+// per-stage table (Mem = false) or the table in memory through L1/L2 (Mem = true).
+template <int Pol, bool Mem>
+struct TwSrc {
+  TwT<Pol> *lds;  // the LDS copy (unused when Mem)
+  __device__ __forceinline__ TwT<Pol> at(int i, const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) const {
+    if constexpr (Mem) return twg[i];
+    else return lds[i];
+  }
+};
+
 struct Mod {
   T p, p2, j;
 };
@@ -206,7 +215,8 @@ constexpr int kVec = 16 / sizeof(T);
 // with consecutive positions read consecutive entries.
 // LowRound: b_lo = 0, the twiddle indices are compile-time constants and are
 // read from global memory with scalar loads; the butterflies with twiddle 1
-// skip the product.  Otherwise the twiddles come from the LDS copy `tws`.
+// skip the product.  Otherwise the twiddles come from `tws` (the LDS copy of the
+// table, or the table in memory: TwSrc).
 // Src/Dst provide load2/store2 of one position given as a per-lane part plus a
 // uniform part with disjoint bits, and load_vec/store_vec of kVec consecutive
 // positions when their kContig flag is set.
@@ -287,8 +297,8 @@ struct DefersIn<S, std::void_t<decltype(S::kDeferIn)>> {
 };
 
 // The K stages of one round on a thread's 2^K words v (positions base | (e << b_lo)).
-template <int Pol, int N_LOG, int K, bool LowRound, bool INV, class FoldT>
-__device__ __forceinline__ void round_stages(T (&v)[1 << K], int b_lo, int base, const TwT<Pol> *tws,
+template <int Pol, int N_LOG, int K, bool LowRound, bool INV, class FoldT, class TwS>
+__device__ __forceinline__ void round_stages(T (&v)[1 << K], int b_lo, int base, const TwS &tws,
                                             const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m,
                                             const FoldT &fold) {
   constexpr int M = 1 << K;
@@ -317,7 +327,7 @@ __device__ __forceinline__ void round_stages(T (&v)[1 << K], int b_lo, int base,
           const int b = b_lo + hb;
           const int pos = base | (e << b_lo);
           const int ti = (1 << b) + (pos & ((1 << b) - 1));
-          const TwT<Pol> tw = tw_global_here(N_LOG) ? twg[ti] : tws[ti];
+          const TwT<Pol> tw = tws.at(ti, twg);
           bfly<Pol, INV>(v[e], v[e | (1 << hb)], tw, m);
         }
       }
@@ -331,8 +341,8 @@ struct NoMid {
 };
 
 template <int Pol, int N_LOG, int K, bool LowRound, bool ZU = false, class Src, class Dst, class Hook = NoHook,
-          class FoldT = NoFold, bool INV = kInverse, class MidT = NoMid>
-__device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwT<Pol> *tws,
+          class FoldT = NoFold, bool INV = kInverse, class MidT = NoMid, class TwS>
+__device__ __forceinline__ void round_k(int b_lo, int t, int tpt, const TwS &tws,
                                        const HNTT_GLOBAL TwT<Pol> *__restrict__ twg, const Mod &m, const Src &src,
                                        const Dst &dst, const Hook &after_load = Hook{}, const FoldT &fold = FoldT{},
                                        const MidT &mid = MidT{}) {
@@ -684,14 +694,14 @@ struct DeferredIn {
 // Copy of the N-entry heap twiddle table into LDS, in two steps so that its global
 // loads are in flight together with the tile's: load() issues up to kR loads per
 // thread into registers, store() writes them to LDS (and copies any remainder).
-template <int Pol, int N>
+template <int Pol, int N, bool Mem>
 struct TwStage {
   static constexpr int N_LOG2 = __builtin_ctz(N);
   static constexpr int kR = 8;
   TwT<Pol> r[kR];
   int nthr;  // threads in the workgroup
   __device__ __forceinline__ void load(const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) {
-    if constexpr (tw_global_here(N_LOG2)) return;
+    if constexpr (Mem) return;
 #pragma unroll
     for (int j = 0; j < kR; ++j) {
       const int i = threadIdx.x + j * nthr;
@@ -699,7 +709,7 @@ struct TwStage {
     }
   }
   __device__ __forceinline__ void store(TwT<Pol> *tws, const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) const {
-    if constexpr (tw_global_here(N_LOG2)) return;
+    if constexpr (Mem) return;
 #pragma unroll
     for (int j = 0; j < kR; ++j) {
       const int i = threadIdx.x + j * nthr;
@@ -815,8 +825,12 @@ __global__ void __launch_bounds__(kMaxPassThreads)
     g = threadIdx.x / TPT;
   }
   const size_t C = (size_t)1 << a.log_other;
-  TwT<Pol> *tws = reinterpret_cast<TwT<Pol> *>(smem_raw);
-  T *tile = tw_global_here(N_LOG) ? reinterpret_cast<T *>(smem_raw) : reinterpret_cast<T *>(tws + N);
+  // the high and middle rounds' twiddles: from memory in forward row passes of long
+  // rows, else from an LDS copy of the table placed before the tile
+  constexpr bool kTwMem = tw_global(N_LOG, HNTT_WORD, !Cols && !kInverse);
+  TwT<Pol> *const tw_lds = reinterpret_cast<TwT<Pol> *>(smem_raw);
+  const TwSrc<Pol, kTwMem> tws{tw_lds};
+  T *tile = kTwMem ? reinterpret_cast<T *>(smem_raw) : reinterpret_cast<T *>(tw_lds + N);
 
   // One tile (transform b, unit) per workgroup.  Blocks are dealt to the 8 XCDs
   // round-robin; each XCD takes a contiguous eighth of the units for every transform,
@@ -980,7 +994,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
       // The twiddle table's loads are issued first and written to LDS only after
       // the tile's loads are in flight: one memory round trip before the stages.
       const int nthr = G * TPT;  // blockDim.x
-      TwStage<Pol, N> stage;
+      TwStage<Pol, N, kTwMem> stage;
       stage.nthr = nthr;
       stage.load(twg);
       hi_load();
@@ -1014,7 +1028,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
               const int c = copyout_chunk<kCh>(t + j * TPT) * kVec;
               *reinterpret_cast<Vec16 *>(tile + g * kPitch + c + ((c >> 5) << 2)) = q[j];
             }
-            stage.store(tws, twg);
+            stage.store(tw_lds, twg);
             hi_store();
             __syncthreads();  // tile, twiddle table and high factors staged
             const LdsEdgeIO<EdgeT> lin{lio, edge};
@@ -1026,7 +1040,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           // the row's words are loaded raw, the twiddle table and high factors are
           // staged meanwhile, and the split twiddle is applied after the barrier
           const auto staged = [&]() {
-            stage.store(tws, twg);
+            stage.store(tw_lds, twg);
             hi_store();
             __syncthreads();  // twiddle table and high factors staged
           };
@@ -1036,14 +1050,14 @@ __global__ void __launch_bounds__(kMaxPassThreads)
         } else if constexpr (TT) {
           // the split twiddle's products follow the loads and would all have to
           // finish before a barrier placed after them: the table goes first
-          stage.store(tws, twg);
+          stage.store(tw_lds, twg);
           hi_store();
           __syncthreads();  // twiddle table and high factors staged
           if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio, NoHook{}, fold);
           else round_k<Pol, N_LOG, KH, false>(KM + KL, t, TPT, tws, twg, m, gio, lio, NoHook{}, fold);
         } else {
           const auto staged = [&]() {
-            stage.store(tws, twg);
+            stage.store(tw_lds, twg);
             __syncthreads();  // twiddle table staged
           };
           if (a.zero_upper) round_k<Pol, N_LOG, KH, false, true>(KM + KL, t, TPT, tws, twg, m, gio, lio, staged);
@@ -1063,7 +1077,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           // the product and the inverse low round, so they go back to their own tile
           // places with no barrier; the inverse table and high factors replace the
           // forward ones (read only before the barrier above) meanwhile.
-          TwStage<Pol, N> stage_i;
+          TwStage<Pol, N, kTwMem> stage_i;
           stage_i.nthr = nthr;
           stage_i.load(twg_i);
           hi_load_from(edge_i.tt);
@@ -1074,7 +1088,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
           }
           round_k<Pol, N_LOG, KL, true, false, LdsIO<false>, LdsIO<false>, NoHook, NoFold, false>(
               0, t, TPT, tws, twg, m, lio, lio, NoHook{}, NoFold{}, fmid);
-          stage_i.store(tws, twg_i);
+          stage_i.store(tw_lds, twg_i);
           hi_store();
           __syncthreads();  // product tile, inverse table and inverse high factors complete
           if constexpr (KM > 0) {
@@ -1136,7 +1150,7 @@ __global__ void __launch_bounds__(kMaxPassThreads)
         }
       } else {
         round_k<Pol, N_LOG, KL, true>(0, t, TPT, tws, twg, m, gio, lio);
-        stage.store(tws, twg);
+        stage.store(tw_lds, twg);
         hi_store();
         __syncthreads();  // tile, twiddle table and high factors complete
         if constexpr (KM > 0) {
