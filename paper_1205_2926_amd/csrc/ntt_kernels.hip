@@ -107,8 +107,9 @@ size_t pass_lds_bytes(const PassParams &pp) {
                             ? N + N / 32
                             : row_padded_len(N) + row_skew(pp.n, sp.kh, sp.km, sp.kl, pp.word_bits);
   // (no LDS copy of the twiddle table where tw_global says so)
-  const bool fwd_rows = pp.kind != PassKind::kCols && !pp.inverse;
-  const size_t bytes = wb * ((tw_global(pp.n, pp.word_bits, fwd_rows) ? 0 : 2 * N) + padded * pp.group);
+  const bool fwd = pp.kind != PassKind::kCols && !pp.inverse;
+  const bool mem = tw_global(pp.n, pp.word_bits, fwd, pp.kind == PassKind::kWhole);
+  const size_t bytes = wb * ((mem ? 0 : 2 * N) + padded * pp.group);
   return bytes <= 160 * 1024 ? bytes : 0;
 }
 

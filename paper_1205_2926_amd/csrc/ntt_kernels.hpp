@@ -103,14 +103,18 @@ constexpr size_t row_skew(int n, int kh, int km, int kl, int word_bits) {
 // compile-time twiddles read them from global memory (L1/L2) instead of an LDS
 // copy of the table.  For 64-bit words the copy (16-byte entries: a third of
 // the LDS next to a 2^11-word tile) would cost a workgroup per CU.  For 32-bit
-// words the forward row pass (and the whole-transform pass, the same kernel) of
-// 2^10 words and more reads from memory: without the 8 KB copy four workgroups of
-// eight rows fit a CU instead of three, and the staging registers are freed
-// (2^10-word rows: 114 against 124 us per 64 x 2^20 launch).  The column passes
-// and the inverse row pass keep the copy (from memory they ran 9-16% slower), and
-// so do shorter forward rows (the 4096-product batch's 2^6- to 2^9-word passes
-// ran 4-6% slower from memory).
-constexpr bool tw_global(int n, int word_bits, bool fwd_rows) { return word_bits == 64 || (fwd_rows && n >= 10); }
+// words, forward passes over rows or whole transforms (fwd) read from memory at
+// 2^10 words: without the 8 KB copy four workgroups of eight rows fit a CU
+// instead of three, and the staging registers are freed (2^10-word rows: 114
+// against 124 us per 64 x 2^20 launch).  Above 2^10 words only whole transforms
+// (whole) do: the product batch's 2^11- and 2^12-word transforms ran 4% faster
+// from memory, the large-integer batch's 2^11-word rows 2% slower.  The column
+// passes and the inverse passes keep the copy (from memory they ran 9-16%
+// slower), and so do shorter forward passes (the product batch's 2^6- to
+// 2^9-word passes ran 4-6% slower from memory).
+constexpr bool tw_global(int n, int word_bits, bool fwd, bool whole) {
+  return word_bits == 64 || (fwd && (n == 10 || (n > 10 && whole)));
+}
 
 // Threads per sub-transform: one group of the largest round each.
 inline int pass_tpt(int n, int word_bits, bool whole = false) {

@@ -24,7 +24,7 @@
 //
 // Twiddles of the high and middle rounds depend on the thread's low position
 // bits and are read from an LDS copy of the table (from the table in memory, through
-// L1, in forward row passes of 2^10 words and more: tw_global); twiddles of the low round
+// L1, in some forward passes: tw_global); twiddles of the low round
 // are uniform across the workgroup (their indices are compile-time multiples of
 // 2^(n-1-b)), so they come straight from global memory through scalar loads,
 // and the butterflies whose twiddle is 1 skip the product entirely.  The split
@@ -825,9 +825,10 @@ __global__ void __launch_bounds__(kMaxPassThreads)
     g = threadIdx.x / TPT;
   }
   const size_t C = (size_t)1 << a.log_other;
-  // the high and middle rounds' twiddles: from memory in forward row passes of long
-  // rows, else from an LDS copy of the table placed before the tile
-  constexpr bool kTwMem = tw_global(N_LOG, HNTT_WORD, !Cols && !kInverse);
+  // the high and middle rounds' twiddles: from memory in some forward passes (a row
+  // pass carries the split twiddle, a whole-transform pass does not), else from an
+  // LDS copy of the table placed before the tile
+  constexpr bool kTwMem = tw_global(N_LOG, HNTT_WORD, !Cols && !kInverse, !Cols && !TT);
   TwT<Pol> *const tw_lds = reinterpret_cast<TwT<Pol> *>(smem_raw);
   const TwSrc<Pol, kTwMem> tws{tw_lds};
   T *tile = kTwMem ? reinterpret_cast<T *>(smem_raw) : reinterpret_cast<T *>(tw_lds + N);
@@ -1315,6 +1316,9 @@ hipError_t HNTT_LAUNCH_NAME(const PassParams &pp, const BatchPtrs &ptrs, hipStre
   const int blocks = (int)total;
   using namespace HNTT_NS;
   const bool tt = pp.table ? pp.slots[0].tt != nullptr : pp.tt != nullptr;
+  // a row pass applies the split twiddle and a whole-transform pass does not: the
+  // kernel's table placement (and the LDS size above) relies on it
+  if (!cols && tt != (pp.kind == PassKind::kRows)) return hipErrorInvalidValue;
   const bool fuse = pp.fuse_inverse;
   switch (pp.policy) {
     case kPolicyLazy:
