@@ -148,11 +148,11 @@ __device__ __forceinline__ TwT<Pol> buf_load_tw(__amdgpu_buffer_rsrc_t r, uint32
   }
 }
 
-// The modulus of a launch: p, 2p and (Montgomery policy) p^-1 mod beta.
 // Where the rounds read the twiddles that are not compile-time: an LDS copy of the
 // per-stage table (Mem = false) or the table in memory through L1/L2 (Mem = true).
 template <int Pol, bool Mem>
 struct TwSrc {
+  static constexpr bool kMem = Mem;
   TwT<Pol> *lds;  // the LDS copy (unused when Mem)
   __device__ __forceinline__ TwT<Pol> at(int i, const HNTT_GLOBAL TwT<Pol> *__restrict__ twg) const {
     if constexpr (Mem) return twg[i];
@@ -160,6 +160,7 @@ struct TwSrc {
   }
 };
 
+// The modulus of a launch: p, 2p and (Montgomery policy) p^-1 mod beta.
 struct Mod {
   T p, p2, j;
 };
